@@ -1,0 +1,248 @@
+"""Pins of the serial HK oracle against results fixed by the paper and by the
+mathematics, independent of the oracle's own code (runs on the CPU).
+
+* brute-force flood fill on every occupancy pattern of tiny boxes, all masks;
+* brute-force flood fill on random boxes up to 16^3;
+* the library routine scipy.ndimage.label (+ separate wrap merge);
+* closed forms: empty, full, site checkerboard (the V/2 bound of Sec. 3),
+  the Sec. 3 block-checkerboard benchmark lattice, rows with a gap,
+  serpentine and comb paths, capsule interiors;
+* hand-worked fixtures in tests/golden/ (Sec. 2 rules, Sec. 3 wraps, the
+  Sec. 2 condition on special float values);
+* invariants on the named workloads.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from golden_io import all_fixtures, load as load_fixture
+from paper_1405_1931_amd import workloads as W
+from pins import bfs_label, check_invariants, scipy_label
+
+ALL_MASKS = range(8)
+
+
+def _same(a, b):
+    la, ka, sa = a
+    lb, kb, sb = b
+    assert ka == kb
+    assert np.array_equal(la, lb)
+    assert np.array_equal(sa, sb)
+
+
+# ---------------------------------------------------------------- brute force
+
+TINY_SHAPES = [(1, 1, 1), (1, 1, 2), (1, 1, 5), (1, 2, 2), (2, 2, 2), (1, 3, 3), (3, 1, 3),
+               (2, 1, 5), (1, 2, 5), (5, 2, 1), (1, 1, 10)]
+
+
+@pytest.mark.parametrize("shape", TINY_SHAPES)
+def test_exhaustive_tiny_vs_bfs(shape, oracle_lib):
+    """Every occupancy pattern of the box, every periodic mask."""
+    n = int(np.prod(shape))
+    for bits in range(1 << n):
+        occ = np.array([(bits >> i) & 1 for i in range(n)], dtype=bool).reshape(shape)
+        phi = np.where(occ, np.float32(0.5), np.float32(-0.5))
+        for mask in ALL_MASKS:
+            _same(oracle.label(phi, mask, lib=oracle_lib), bfs_label(phi, mask))
+
+
+@pytest.mark.parametrize("shape", [(1, 3, 4), (2, 2, 3), (3, 2, 2), (1, 1, 12)])
+def test_exhaustive_12_sites_vs_bfs(shape, oracle_lib):
+    n = 12
+    rng = np.random.default_rng(12)
+    for bits in range(1 << n):
+        occ = np.array([(bits >> i) & 1 for i in range(n)], dtype=bool).reshape(shape)
+        phi = np.where(occ, np.float32(1), np.float32(-1))
+        mask = int(rng.integers(0, 8))
+        _same(oracle.label(phi, mask, lib=oracle_lib), bfs_label(phi, mask))
+
+
+@pytest.mark.parametrize("p", [0.1, 0.3116, 0.5, 0.9])
+def test_random_boxes_vs_bfs(p, oracle_lib):
+    rng = np.random.default_rng(int(p * 1000))
+    for trial in range(24):
+        shape = tuple(int(v) for v in rng.integers(1, 17, size=3))
+        phi = W.percolation(shape, p, seed=int(rng.integers(1 << 30)))
+        mask = trial % 8
+        _same(oracle.label(phi, mask, lib=oracle_lib), bfs_label(phi, mask))
+
+
+# ----------------------------------------------------------- library routine
+
+@pytest.mark.parametrize("mask", ALL_MASKS)
+def test_vs_scipy_64cube(mask, oracle_lib):
+    for p in (0.2, 0.3116, 0.45):
+        phi = W.percolation((64, 64, 64), p, seed=100 + mask)
+        _same(oracle.label(phi, mask, lib=oracle_lib), scipy_label(phi, mask))
+
+
+def test_vs_scipy_odd_shapes(oracle_lib):
+    rng = np.random.default_rng(7)
+    for trial in range(16):
+        shape = tuple(int(v) for v in rng.integers(1, 90, size=3))
+        phi = W.percolation(shape, float(rng.uniform(0.1, 0.7)), seed=trial)
+        mask = int(rng.integers(0, 8))
+        _same(oracle.label(phi, mask, lib=oracle_lib), scipy_label(phi, mask))
+
+
+def test_config1_vs_scipy_and_invariants(oracle_lib):
+    phi, mask = W.config(1)
+    out = oracle.label(phi, mask, lib=oracle_lib)
+    _same(out, scipy_label(phi, mask))
+    check_invariants(phi, mask, *out)
+    # K/N near the value expected for critical site percolation on 64^3
+    assert 0.04 < out[1] / phi.size < 0.07
+
+
+# ---------------------------------------------------------------- closed forms
+
+@pytest.mark.parametrize("mask", ALL_MASKS)
+@pytest.mark.parametrize("shape", [(1, 1, 1), (3, 5, 7), (16, 16, 16), (2, 1, 9)])
+def test_empty_and_full(shape, mask, oracle_lib):
+    lab, k, s = oracle.label(W.constant(shape, -1.0), mask, lib=oracle_lib)
+    assert k == 0 and not lab.any() and s.size == 0
+    lab, k, s = oracle.label(W.constant(shape, 1.0), mask, lib=oracle_lib)
+    assert k == 1 and (lab == 1).all() and list(s) == [int(np.prod(shape))]
+
+
+@pytest.mark.parametrize("shape", [(4, 6, 8), (3, 5, 7), (1, 1, 9), (8, 8, 8)])
+def test_site_checkerboard(shape, oracle_lib):
+    """Sec. 3: at most V/2 clusters, reached by single sites in an
+    alternating pattern.  Non-periodic: every even-parity site is its own
+    cluster, numbered in linear order."""
+    phi = W.site_checkerboard(shape, parity=0)
+    lab, k, s = oracle.label(phi, 0, lib=oracle_lib)
+    n = int(np.prod(shape))
+    assert k == (n + 1) // 2 == oracle_lib.hk_oracle_max_clusters(shape[2], shape[1], shape[0])
+    assert (s == 1).all()
+    even = (phi > 0).ravel()
+    expect = np.where(even, np.cumsum(even), 0).reshape(shape)
+    assert np.array_equal(lab, expect)
+    # periodic with even lengths: wrap partners have opposite parity
+    if all(v % 2 == 0 for v in shape):
+        lab7, k7, _ = oracle.label(phi, 7, lib=oracle_lib)
+        assert k7 == n // 2 and np.array_equal(lab7, expect)
+
+
+@pytest.mark.parametrize("b", [1, 2, 4, 8])
+@pytest.mark.parametrize("mask", [0, 7])
+def test_block_checkerboard(b, mask, oracle_lib):
+    """The Sec. 3 benchmark lattice: blocks that touch only at corners and
+    alternate in sign.  With an even number of blocks per axis every +1
+    block is one cluster; numbering by lowest site gives
+    label = 1 + (K'*nby + J)*(nbx/2) + floor(I/2) for block (I, J, K')."""
+    n = 32
+    phi = W.block_checkerboard((n, n, n), (b, b, b))
+    lab, k, s = oracle.label(phi, mask, lib=oracle_lib)
+    nb = n // b
+    assert k == nb ** 3 // 2
+    assert (s == b ** 3).all()
+    z, y, x = np.ogrid[:n, :n, :n]
+    I, J, K = x // b, y // b, z // b
+    occ = (I + J + K) % 2 == 0
+    # lowest site of block (I,J,K) is its corner; blocks are ordered by
+    # (K, J, I) of their corners, and within a (K, J) block-row the occupied
+    # blocks are every other I.
+    expect = np.where(occ, 1 + (K * nb + J) * (nb // 2) + I // 2, 0)
+    assert np.array_equal(lab, expect)
+
+
+@pytest.mark.parametrize("nx", [2, 5, 64, 70])
+def test_row_with_gap(nx, oracle_lib):
+    """A full x-row with one interior gap: two clusters, one if x wraps."""
+    phi = W.constant((1, 1, nx), 1.0)
+    gap = nx // 2
+    phi[0, 0, gap] = -1
+    _, k0, s0 = oracle.label(phi, 0, lib=oracle_lib)
+    _, k1, s1 = oracle.label(phi, 1, lib=oracle_lib)
+    if 0 < gap < nx - 1:
+        assert k0 == 2 and list(s0) == [gap, nx - 1 - gap]
+    assert k1 == 1 and list(s1) == [nx - 1]
+
+
+@pytest.mark.parametrize("shape", [(5, 9, 11), (1, 15, 16), (3, 30, 7)])
+def test_serpentine_and_comb(shape, oracle_lib):
+    for gen in (W.serpentine, W.comb):
+        phi = gen(shape)
+        for mask in ALL_MASKS:
+            lab, k, s = oracle.label(phi, mask, lib=oracle_lib)
+            assert k == 1, gen.__name__
+            assert list(s) == [int((phi > 0).sum())]
+
+
+def test_capsules_closed_form(oracle_lib):
+    """Sec. 6: closed shells separate each interior pocket from the exterior.
+    Expect one exterior cluster containing site 0 (label 1) and one cluster
+    per capsule whose size is the number of sites inside the inner
+    ellipsoid."""
+    shape = (128, 64, 64)
+    phi, caps = W.capsules(shape, 20, 6.0, 15.0, 2.0, seed=44)
+    lab, k, s = oracle.label(phi, 4, lib=oracle_lib)
+    assert k == 1 + len(caps)
+    assert lab.flat[0] == 1
+    interior = W.capsule_interior_counts(shape, caps, 2.0)
+    assert sorted(interior) == sorted(s[1:].tolist())
+    shell = int((phi < 0).sum())
+    assert s[0] == phi.size - shell - sum(interior)
+
+
+# ----------------------------------------------------------- golden fixtures
+
+@pytest.mark.parametrize("name", all_fixtures())
+def test_golden_fixture(name, oracle_lib):
+    phi, cases = load_fixture(name)
+    assert cases
+    for c in cases:
+        lab, k, s = oracle.label(phi, c["mask"], lib=oracle_lib)
+        assert k == c["k"], (name, c["mask"])
+        assert np.array_equal(s, c["sizes"]), (name, c["mask"])
+        assert np.array_equal(lab, c["labels"]), (name, c["mask"])
+        # the fixtures agree with flood fill too
+        _same((lab, k, s), bfs_label(phi, c["mask"]))
+
+
+# --------------------------------------------------------------- invariants
+
+def test_special_values_everywhere(oracle_lib):
+    """NaN / signed zeros / denormals / infinities scattered in a lattice."""
+    rng = np.random.default_rng(3)
+    phi = W.percolation((12, 13, 14), 0.5, seed=9)
+    specials = np.array([0x7FC00000, 0x80000000, 0x00000000, 0x00000001, 0x80000001,
+                         0x7F800000, 0xFF800000, 0x7F800001, 0x007FFFFF], dtype=np.uint32).view(np.float32)
+    idx = rng.integers(0, phi.size, size=400)
+    phi.ravel()[idx] = specials[rng.integers(0, specials.size, size=idx.size)]
+    for mask in ALL_MASKS:
+        out = oracle.label(phi, mask, lib=oracle_lib)
+        _same(out, bfs_label(phi, mask))
+        check_invariants(phi, mask, *out)
+
+
+def test_invariants_config4_scaled(oracle_lib):
+    phi, mask = W.config(4, scale=2)
+    out = oracle.label(phi, mask, lib=oracle_lib)
+    check_invariants(phi, mask, *out)
+
+
+def test_invariants_config2_scaled(oracle_lib):
+    phi, mask = W.config(2, scale=4)
+    out = oracle.label(phi, mask, lib=oracle_lib)
+    check_invariants(phi, mask, *out)
+    _same(out, scipy_label(phi, mask))
+
+
+def test_argument_errors(oracle_lib):
+    import ctypes
+
+    buf = np.zeros(8, np.float32)
+    lab = np.zeros(8, np.int32)
+    k = ctypes.c_int64(-7)
+    for args in [(0, 1, 1, 0), (1, 0, 1, 0), (1, 1, -1, 0), (2, 2, 2, 8)]:
+        rc = oracle_lib.hk_oracle_label(buf.ctypes.data, *args, lab.ctypes.data, ctypes.addressof(k), None)
+        assert rc == -1 and k.value == -7
+    rc = oracle_lib.hk_oracle_label(buf.ctypes.data, 2048, 2048, 1024, 0, lab.ctypes.data, ctypes.addressof(k), None)
+    assert rc == -2 and k.value == -7
