@@ -1,0 +1,257 @@
+#!/usr/bin/env python3
+"""Benchmark of the GPU Hoshen-Kopelman path on one MI355X.
+
+Default workload: site percolation on a 1024^3 lattice at p = 0.3116,
+periodic in x, y and z (phi = U(0,1) - (1 - p), seed 3).  One step = one
+hk_label call = every phase of the path (occupancy, brick labelling, face
+merge, flatten, canonical ranking, relabel + sizes) with phi already in HBM.
+
+Prints ONE JSON line with the throughput in Gsites/s, the roofline of the
+dominant kernel (algorithmic bytes over its live-measured average duration,
+HIP events on the launch stream), the oracle timed on a bounded slab of the
+same workload on the host cores, and the batched-vs-per-lattice comparison
+on the 256-lattice stream.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1405_1931_amd", "csrc", f)
+                  for f in ("hk_device.h", "hk_kernels.hip")]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(kernel, n, k):
+    """Bytes a kernel must move by the method's definition: phi is read once
+    (4 B/site), labels written once (4 B/site), sizes written once
+    (8 B/cluster) plus K (8 B).  Every other byte is implementation
+    overhead, so the other kernels have no algorithmic share."""
+    if kernel == "k_pack":
+        return 4 * n
+    if kernel == "k_write":
+        return 4 * n + 8 * k
+    return 0
+
+
+def load_traffic(kernel, workload_tag):
+    """HBM traffic of `kernel` from the committed rocprofv3 counter summary,
+    or None when it is missing or was taken on other kernel sources."""
+    path = os.path.join(PROFILES, f"traffic_{kernel}_{workload_tag}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("source_sha") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(phi_np, mask, planes):
+    """The serial oracle on the first `planes` z-planes of the workload."""
+    import numpy as np
+
+    import oracle
+
+    lib = oracle.load()
+    sample = np.ascontiguousarray(phi_np[:planes])
+    t0 = time.perf_counter()
+    _, k, _ = oracle.label(sample, mask, lib=lib)
+    dt = time.perf_counter() - t0
+    n = sample.size
+    return {"value": round(n / dt / 1e9, 4), "unit": "Gsites/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {planes} z-planes of the workload ({sample.shape[2]}x{sample.shape[1]}x{planes}"
+                      f" = {n} sites, mask {mask}), serial C oracle, one thread, {dt:.2f} s, K={k}",
+            "host_cpu": cpu_model(), "host_threads": os.cpu_count()}
+
+
+def bench_batched(hk, torch, warmup, reps):
+    """Config 5 stream (256 uneven lattices): back-to-back hk_label calls on
+    one stream versus one hk_label_batched launch, same jobs, same buffers."""
+    from paper_1405_1931_amd import workloads as W
+
+    t0 = time.time()
+    jobs = W.stream()
+    log(f"config-5 stream generated in {time.time() - t0:.1f} s")
+    bufs = []
+    total = 0
+    for j in jobs:
+        phi = torch.from_numpy(j.phi).cuda()
+        nz, ny, nx = phi.shape
+        total += phi.numel()
+        bufs.append((phi, j.mask, torch.empty_like(phi, dtype=torch.int32),
+                     torch.zeros(1, dtype=torch.int64, device="cuda"),
+                     torch.empty(max(1, hk.max_clusters(nx, ny, nz)), dtype=torch.int64, device="cuda")))
+    torch.cuda.synchronize()
+
+    def per_lattice():
+        for b in bufs:
+            hk.label_into(*b)
+
+    def batched():
+        hk.label_batched_into(bufs)
+
+    out = {}
+    for name, fn in (("per_lattice", per_lattice), ("batched", batched)):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": round(ms, 4), "gsites_per_s": round(total / ms / 1e6, 3),
+                     "jobs_per_s": round(len(bufs) / ms * 1e3, 1)}
+    out["speedup"] = round(out["per_lattice"]["ms"] / out["batched"]["ms"], 2)
+    out["jobs"] = len(bufs)
+    out["sites"] = total
+    assert hk.device_error() == 0
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--edge", type=int, default=1024, help="lattice edge (default: the 1024^3 workload)")
+    ap.add_argument("--cpu-planes", type=int, default=384, help="z-planes of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build labels one lattice (or one batch) per GPU and "
+              "has no multi-GPU path; run it with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1405_1931_amd as hk
+    from paper_1405_1931_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    edge = args.edge
+    mask = 7
+    t0 = time.time()
+    phi_np = W.percolation((edge, edge, edge), W.P_SITE, seed=3)
+    log(f"generated {edge}^3 phi in {time.time() - t0:.1f} s")
+    phi = torch.from_numpy(phi_np).cuda()
+    n = phi.numel()
+    labels = torch.empty_like(phi, dtype=torch.int32)
+    kbuf = torch.zeros(1, dtype=torch.int64, device="cuda")
+    sizes = torch.empty(hk.max_clusters(edge, edge, edge), dtype=torch.int64, device="cuda")
+    by, bz = hk.get_brick(edge, edge, edge)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        hk.label_into(phi, mask, labels, kbuf, sizes)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(args.steps):
+        hk.label_into(phi, mask, labels, kbuf, sizes)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    k = int(kbuf.item())
+    err = hk.device_error()
+    assert err == 0, f"device check fired: {err}"
+    log(f"{ms:.3f} ms/step, K={k}")
+
+    kernels = {}
+    roofline = None
+    if not args.no_profile:
+        hk.profile_enable(True)
+        reps = max(1, min(args.steps, 10))
+        for _ in range(reps):
+            hk.label_into(phi, mask, labels, kbuf, sizes)
+        torch.cuda.synchronize()
+        tot, calls = hk.profile_read()
+        hk.profile_enable(False)
+        kernels = {name: round(v / calls, 4) for name, v in tot.items()}
+        dom = max(kernels, key=kernels.get)
+        alg = algorithmic_bytes(dom, n, k)
+        dur_s = kernels[dom] / 1e3
+        achieved = alg / dur_s / 1e9 if alg else 0.0
+        roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": load_traffic(dom, f"percolation{edge}"),
+                    "avg_ms": kernels[dom], "algorithmic_bytes": alg}
+        log(f"kernels (ms/launch): {kernels}")
+
+    path_bytes = 8 * n + 8 * k + 8
+    result = {
+        "metric": "Gsites/s labelled (1024^3 percolation p=0.3116, periodic)",
+        "value": round(n / (ms / 1e3) / 1e9, 3),
+        "unit": "Gsites/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (seeded numpy PCG64 percolation field, resident in HBM)",
+        "config": {"workload": f"site percolation {edge}^3 p=0.3116 periodic xyz", "nx": edge, "ny": edge,
+                   "nz": edge, "periodic_mask": mask, "brick": [64, by, bz], "clusters": k},
+        "path_roofline": {"algorithmic_bytes": path_bytes, "achieved": round(path_bytes / (ms / 1e3) / 1e9, 1),
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(path_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "roofline": roofline,
+        "kernels_ms": kernels,
+    }
+    del labels, sizes
+    if not args.no_batched:
+        torch.cuda.empty_cache()
+        result["batched"] = bench_batched(hk, torch, warmup=2, reps=5)
+        log(f"batched: {result['batched']}")
+    if not args.no_cpu_baseline:
+        planes = min(args.cpu_planes, edge)
+        result["cpu_baseline"] = cpu_baseline(phi_np, mask, planes)
+        log(f"cpu baseline: {result['cpu_baseline']}")
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,188 @@
+"""MI355X-native Hoshen-Kopelman cluster labelling (Python binding).
+
+Every step of the labelling runs in the HIP kernels of ``libhk.so``; this
+module only checks tensors and passes device pointers and the current HIP
+stream through the C-ABI declared in ``include/hk.h``.  PyTorch provides the
+device memory and the stream.
+
+    labels, k, sizes = paper_1405_1931_amd.label(phi, periodic=(True, True, True))
+
+``phi`` is a float32 CUDA/HIP tensor of shape (nz, ny, nx); ``labels`` comes
+back as int32 of the same shape (0 = medium, clusters 1..K numbered by their
+lowest linear site), ``sizes`` as int64[K].
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+
+__all__ = [
+    "label", "label_into", "label_batched", "label_batched_into", "max_clusters", "workspace_bytes",
+    "batched_workspace_bytes", "reserve", "release", "set_brick", "get_brick", "set_brick_for_shape",
+    "device_error", "mask_of",
+]
+
+
+def mask_of(periodic) -> int:
+    if isinstance(periodic, int):
+        if not 0 <= periodic <= 7:
+            raise ValueError("periodic mask must be in 0..7")
+        return periodic
+    px, py, pz = periodic
+    return (1 if px else 0) | (2 if py else 0) | (4 if pz else 0)
+
+
+def _stream_handle(stream=None):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_phi(phi):
+    import torch
+
+    if not isinstance(phi, torch.Tensor) or phi.dtype != torch.float32 or not phi.is_cuda:
+        raise TypeError("phi must be a float32 tensor on the GPU")
+    if phi.dim() != 3 or not phi.is_contiguous():
+        raise ValueError("phi must be a contiguous (nz, ny, nx) tensor")
+
+
+def max_clusters(nx: int, ny: int, nz: int) -> int:
+    return int(_lib.load().hk_max_clusters(nx, ny, nz))
+
+
+def workspace_bytes(nx: int, ny: int, nz: int) -> int:
+    v = int(_lib.load().hk_workspace_bytes(nx, ny, nz))
+    _lib.check(v if v < 0 else 0, "hk_workspace_bytes")
+    return v
+
+
+def label_into(phi, mask, labels, n_clusters, sizes=None, stream=None):
+    """Enqueue one labelling into caller-owned tensors; no synchronisation.
+
+    labels: int32 (nz, ny, nx); n_clusters: int64 tensor of >= 1 element;
+    sizes: int64 tensor with >= max_clusters entries, or None.
+    """
+    _check_phi(phi)
+    nz, ny, nx = phi.shape
+    lib = _lib.load()
+    rc = lib.hk_label(
+        ctypes.c_void_p(phi.data_ptr()), nx, ny, nz, mask_of(mask),
+        ctypes.c_void_p(labels.data_ptr()), ctypes.c_void_p(n_clusters.data_ptr()),
+        ctypes.c_void_p(sizes.data_ptr()) if sizes is not None else None,
+        _stream_handle(stream),
+    )
+    _lib.check(rc, "hk_label")
+
+
+def label(phi, periodic=0, stream=None, sizes=True):
+    """Label one lattice; returns (labels int32, K, sizes int64[K] or None).
+
+    Synchronises only to read K back to the host.
+    """
+    import torch
+
+    _check_phi(phi)
+    nz, ny, nx = phi.shape
+    labels = torch.empty_like(phi, dtype=torch.int32)
+    k = torch.zeros(1, dtype=torch.int64, device=phi.device)
+    sz = torch.empty(max(1, max_clusters(nx, ny, nz)), dtype=torch.int64, device=phi.device) if sizes else None
+    label_into(phi, periodic, labels, k, sz, stream=stream)
+    kk = int(k.item())
+    return labels, kk, (sz[:kk] if sz is not None else None)
+
+
+def _jobs_array(jobs):
+    arr = (_lib.HkJob * max(1, len(jobs)))()
+    for i, j in enumerate(jobs):
+        phi, mask, labels, kbuf, sizes = j
+        _check_phi(phi)
+        nz, ny, nx = phi.shape
+        arr[i] = _lib.HkJob(phi.data_ptr(), nx, ny, nz, mask_of(mask), labels.data_ptr(), kbuf.data_ptr(),
+                            sizes.data_ptr() if sizes is not None else None)
+    return arr
+
+
+def batched_workspace_bytes(phis):
+    """Workspace bytes of one batched call over tensors (shapes only)."""
+    arr = (_lib.HkJob * max(1, len(phis)))()
+    for i, phi in enumerate(phis):
+        nz, ny, nx = phi.shape
+        arr[i] = _lib.HkJob(None, nx, ny, nz, 0, None, None, None)
+    v = int(_lib.load().hk_batched_workspace_bytes(arr, len(phis)))
+    _lib.check(v if v < 0 else 0, "hk_batched_workspace_bytes")
+    return v
+
+
+def label_batched_into(jobs, stream=None):
+    """Enqueue one batched launch.  ``jobs`` is a list of
+    (phi, mask, labels, n_clusters, sizes) tensors; no synchronisation."""
+    arr = _jobs_array(jobs)
+    rc = _lib.load().hk_label_batched(arr, len(jobs), _stream_handle(stream))
+    _lib.check(rc, "hk_label_batched")
+
+
+def label_batched(items, stream=None):
+    """Label a list of (phi, periodic) lattices in one batched launch;
+    returns a list of (labels, K, sizes[K])."""
+    import torch
+
+    jobs = []
+    for phi, per in items:
+        _check_phi(phi)
+        nz, ny, nx = phi.shape
+        labels = torch.empty_like(phi, dtype=torch.int32)
+        k = torch.zeros(1, dtype=torch.int64, device=phi.device)
+        sz = torch.empty(max(1, max_clusters(nx, ny, nz)), dtype=torch.int64, device=phi.device)
+        jobs.append((phi, per, labels, k, sz))
+    label_batched_into(jobs, stream=stream)
+    out = []
+    ks = torch.cat([j[3] for j in jobs]).tolist() if jobs else []
+    for j, kk in zip(jobs, ks):
+        out.append((j[2], int(kk), j[4][: int(kk)]))
+    return out
+
+
+def reserve(nbytes: int, stream=None):
+    _lib.check(_lib.load().hk_reserve(int(nbytes), _stream_handle(stream)), "hk_reserve")
+
+
+def release():
+    _lib.load().hk_release()
+
+
+def set_brick(by: int, bz: int):
+    _lib.check(_lib.load().hk_set_brick(by, bz), "hk_set_brick")
+
+
+def get_brick(nx: int, ny: int, nz: int):
+    by, bz = ctypes.c_int32(0), ctypes.c_int32(0)
+    _lib.check(_lib.load().hk_get_brick(nx, ny, nz, ctypes.byref(by), ctypes.byref(bz)), "hk_get_brick")
+    return by.value, bz.value
+
+
+def set_brick_for_shape(nx, ny, nz, by, bz):
+    _lib.check(_lib.load().hk_set_brick_for_shape(nx, ny, nz, by, bz), "hk_set_brick_for_shape")
+
+
+def profile_enable(on: bool = True):
+    _lib.check(_lib.load().hk_profile_enable(1 if on else 0), "hk_profile_enable")
+
+
+def profile_read():
+    """{kernel name: summed ms} over the hk_label calls profiled since the
+    last read, and the number of those calls."""
+    lib = _lib.load()
+    n = int(lib.hk_phase_count())
+    ms = (ctypes.c_float * n)()
+    calls = ctypes.c_int32(0)
+    _lib.check(lib.hk_profile_read(ms, n, ctypes.byref(calls)), "hk_profile_read")
+    return {lib.hk_phase_name(i).decode(): float(ms[i]) for i in range(n)}, calls.value
+
+
+def device_error(stream=None) -> int:
+    code = ctypes.c_int32(0)
+    _lib.load().hk_device_error(_stream_handle(stream), ctypes.byref(code))
+    return code.value

@@ -1,0 +1,89 @@
+"""ctypes binding of libhk.so (argument marshalling only).
+
+The library is built in-tree by ``paper_1405_1931_amd/build.py`` (or
+``__graft_entry__.build()``).  There is no fallback: if the shared library is
+missing, loading raises, so a GPU run can never silently take another path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhk.so")
+HEADER = os.path.join(HERE, "..", "include", "hk.h")
+
+HK_OK = 0
+HK_ERR_INVALID_ARG = -1
+HK_ERR_TOO_LARGE = -2
+HK_ERR_NO_WORKSPACE = -3
+HK_ERR_HIP = -4
+HK_ERR_DEVICE = -5
+
+
+class HkJob(ctypes.Structure):
+    _fields_ = [
+        ("phi", ctypes.c_void_p),
+        ("nx", ctypes.c_int32),
+        ("ny", ctypes.c_int32),
+        ("nz", ctypes.c_int32),
+        ("periodic_mask", ctypes.c_uint32),
+        ("labels", ctypes.c_void_p),
+        ("n_clusters", ctypes.c_void_p),
+        ("sizes", ctypes.c_void_p),
+    ]
+
+
+_SIGS = {
+    "hk_label": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
+                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "hk_label_batched": (ctypes.c_int, [ctypes.POINTER(HkJob), ctypes.c_int32, ctypes.c_void_p]),
+    "hk_max_clusters": (ctypes.c_int64, [ctypes.c_int32] * 3),
+    "hk_workspace_bytes": (ctypes.c_int64, [ctypes.c_int32] * 3),
+    "hk_batched_workspace_bytes": (ctypes.c_int64, [ctypes.POINTER(HkJob), ctypes.c_int32]),
+    "hk_reserve": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p]),
+    "hk_release": (None, []),
+    "hk_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "hk_set_brick": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32]),
+    "hk_get_brick": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    "hk_set_brick_for_shape": (ctypes.c_int, [ctypes.c_int32] * 5),
+    "hk_device_error": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "hk_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
+    "hk_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_float), ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32)]),
+    "hk_phase_count": (ctypes.c_int32, []),
+    "hk_phase_name": (ctypes.c_char_p, [ctypes.c_int32]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libhk.so; raises RuntimeError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"HIP library {path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)  # every declared entry point must be exported
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class HkError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = load()
+        msg = lib.hk_status_string(status).decode()
+        super().__init__(f"{where}: {msg} ({status})")
+        self.status = status
+
+
+def check(status: int, where: str):
+    if status != HK_OK:
+        raise HkError(status, where)

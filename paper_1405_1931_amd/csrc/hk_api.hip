@@ -1,0 +1,429 @@
+// C-ABI of the library: argument checks, brick choice, workspace cache and
+// launches.  See include/hk.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "../../include/hk.h"
+#include "hk_launch.h"
+
+namespace hk {
+namespace {
+
+constexpr int64_t kAlign = 256;
+constexpr int64_t kErrBytes = 256;
+
+int64_t align_up(int64_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int ceil_pow2(int v) {
+    int p = 1;
+    while (p < v && p < (1 << 30)) p <<= 1;
+    return p;
+}
+
+int log2i(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// ---------------------------------------------------------------- bricks
+
+std::mutex g_brick_mu;
+int g_force_by = 0, g_force_bz = 0;
+std::map<uint32_t, std::pair<int, int>> g_tuned;  // bucket -> (by, bz)
+
+uint32_t bucket_of(int nx, int ny, int nz) {
+    return (uint32_t)(log2i(nx) | (log2i(ny) << 8) | (log2i(nz) << 16));
+}
+
+int64_t n_bricks(int nx, int ny, int nz, int by, int bz) {
+    return (int64_t)((nx + 63) / 64) * ((ny + by - 1) / by) * ((nz + bz - 1) / bz);
+}
+
+void heuristic_brick(int nx, int ny, int nz, int *by, int *bz) {
+    int y = std::min(16, ceil_pow2(ny)), z = std::min(16, ceil_pow2(nz));
+    // keep several bricks per compute unit while bricks stay reasonably big
+    while (n_bricks(nx, ny, nz, y, z) < 2048 && y * z > 16) {
+        if (y >= z) y >>= 1; else z >>= 1;
+    }
+    *by = y;
+    *bz = z;
+}
+
+void choose_brick(int nx, int ny, int nz, int *by, int *bz) {
+    std::lock_guard<std::mutex> lk(g_brick_mu);
+    if (g_force_by > 0) {
+        *by = g_force_by;
+        *bz = g_force_bz;
+        return;
+    }
+    auto it = g_tuned.find(bucket_of(nx, ny, nz));
+    if (it != g_tuned.end()) {
+        *by = it->second.first;
+        *bz = it->second.second;
+        return;
+    }
+    heuristic_brick(nx, ny, nz, by, bz);
+}
+
+// ---------------------------------------------------------------- plans
+
+struct Layout {
+    int64_t occ, root, wpre, face, bcount, npar, nkey, nsize, nlpos, rowcnt, blksum, total;
+};
+
+// geometry (no pointers) of one lattice; false if it cannot be handled
+bool make_geo(int nx, int ny, int nz, uint32_t mask, int by, int bz, Geo *g) {
+    std::memset(g, 0, sizeof(*g));
+    g->nx = nx;
+    g->ny = ny;
+    g->nz = nz;
+    g->mask = mask;
+    g->BY = by;
+    g->BZ = bz;
+    g->lby = log2i(by);
+    g->lbz = log2i(bz);
+    g->R = by * bz;
+    g->nbx = (nx + 63) / 64;
+    g->nby = (ny + by - 1) / by;
+    g->nbz = (nz + bz - 1) / bz;
+    const int64_t nb = (int64_t)g->nbx * g->nby * g->nbz;
+    const int exm = std::min(64, nx);
+    const int64_t c1 = 2 * ((g->R + 1) / 2) + 2 * ((exm * bz + 1) / 2) + 2 * ((exm * by + 1) / 2);
+    const int64_t c2 = ((int64_t)exm * g->R + 1) / 2;
+    const int64_t cap = std::max<int64_t>(1, std::min(c1, c2));
+    if (nb > INT32_MAX || nb * cap > INT32_MAX || nb * g->R > ((int64_t)1 << 40)) return false;
+    g->nb = (int)nb;
+    g->cap = (int)cap;
+    g->fstride = 2 * g->R + 128 * bz + 128 * by;
+    g->rows = ny * nz;
+    g->nblk = (g->rows + WG - 1) / WG;
+    return true;
+}
+
+Layout layout_of(const Geo &g, int64_t base) {
+    Layout L;
+    int64_t o = base;
+    auto take = [&](int64_t bytes) {
+        const int64_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    const int64_t words = (int64_t)g.nb * g.R;
+    const int64_t nodes = (int64_t)g.nb * g.cap;
+    L.occ = take(words * 8);
+    L.root = take(words * 8);
+    L.wpre = take(words * 4);
+    L.face = take((int64_t)g.nb * g.fstride * 2);
+    L.bcount = take((int64_t)g.nb * 4);
+    L.npar = take(nodes * 4);
+    L.nkey = take(nodes * 4);
+    L.nsize = take(nodes * 4);
+    L.nlpos = take(nodes * 2);
+    L.rowcnt = take((int64_t)g.rows * 4);
+    L.blksum = take((int64_t)g.nblk * 4);
+    L.total = o - base;
+    return L;
+}
+
+void bind(Geo *g, char *base, const Layout &L) {
+    g->occ = (uint64_t *)(base + L.occ);
+    g->root = (uint64_t *)(base + L.root);
+    g->wpre = (int32_t *)(base + L.wpre);
+    g->face = (uint16_t *)(base + L.face);
+    g->bcount = (int32_t *)(base + L.bcount);
+    g->npar = (int32_t *)(base + L.npar);
+    g->nkey = (int32_t *)(base + L.nkey);
+    g->nsize = (int32_t *)(base + L.nsize);
+    g->nlpos = (uint16_t *)(base + L.nlpos);
+    g->rowcnt = (int32_t *)(base + L.rowcnt);
+    g->blksum = (int32_t *)(base + L.blksum);
+}
+
+int check_shape(int32_t nx, int32_t ny, int32_t nz, uint32_t mask) {
+    if (nx < 1 || ny < 1 || nz < 1 || mask > 7u) return HK_ERR_INVALID_ARG;
+    if ((int64_t)nx * ny * nz > INT32_MAX) return HK_ERR_TOO_LARGE;
+    return HK_OK;
+}
+
+// plan one lattice: geometry with a brick that fits
+int plan_lattice(int32_t nx, int32_t ny, int32_t nz, uint32_t mask, Geo *g) {
+    int by, bz;
+    choose_brick(nx, ny, nz, &by, &bz);
+    if (make_geo(nx, ny, nz, mask, by, bz, g)) return HK_OK;
+    // fall back to smaller bricks (fewer node slots per brick)
+    for (int r = by * bz / 2; r >= 1; r /= 2) {
+        const int y = std::min(by, r), z = std::max(1, r / std::min(by, r));
+        if (make_geo(nx, ny, nz, mask, y, z, g)) return HK_OK;
+    }
+    return HK_ERR_TOO_LARGE;
+}
+
+// ---------------------------------------------------------------- workspace
+
+struct Workspace {
+    char *base = nullptr;
+    int64_t bytes = 0;
+};
+
+std::mutex g_ws_mu;
+std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
+
+// returns a workspace of at least `bytes` (plus the error word) for (device, stream)
+int get_workspace(hipStream_t stream, int64_t bytes, Workspace **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HK_ERR_HIP;
+    Workspace &ws = g_ws[{dev, stream}];
+    const int64_t need = bytes + kErrBytes;
+    if (ws.bytes < need) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return HK_ERR_HIP;
+        if (cs != hipStreamCaptureStatusNone) return HK_ERR_NO_WORKSPACE;
+        if (ws.base) {
+            if (hipStreamSynchronize(stream) != hipSuccess) return HK_ERR_HIP;
+            (void)hipFree(ws.base);
+            ws.base = nullptr;
+            ws.bytes = 0;
+        }
+        const int64_t grow = align_up(need + need / 8);
+        void *p = nullptr;
+        if (hipMalloc(&p, (size_t)grow) != hipSuccess) {
+            (void)hipGetLastError();
+            return HK_ERR_HIP;
+        }
+        if (hipMemset(p, 0, (size_t)kErrBytes) != hipSuccess) {
+            (void)hipFree(p);
+            return HK_ERR_HIP;
+        }
+        ws.base = (char *)p;
+        ws.bytes = grow;
+    }
+    *out = &ws;
+    return HK_OK;
+}
+
+}  // namespace
+
+// exposed to the batched path
+int plan_lattice_ext(int32_t nx, int32_t ny, int32_t nz, uint32_t mask, Geo *g) {
+    return plan_lattice(nx, ny, nz, mask, g);
+}
+int64_t lattice_bytes(const Geo &g) { return layout_of(g, 0).total; }
+void bind_lattice(Geo *g, char *base) { bind(g, base, layout_of(*g, 0)); }
+int acquire_workspace(hipStream_t st, int64_t bytes, char **base, int32_t **err) {
+    Workspace *ws = nullptr;
+    const int rc = get_workspace(st, bytes, &ws);
+    if (rc != HK_OK) return rc;
+    *err = (int32_t *)ws->base;
+    *base = ws->base + kErrBytes;
+    return HK_OK;
+}
+std::mutex &workspace_mutex() { return g_ws_mu; }
+
+// ---------------------------------------------------------------- profiling
+// While enabled, every hk_label call records kPhases + 1 events on its
+// stream around its kernels; hk_profile_read folds them into per-phase sums.
+namespace {
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<std::vector<hipEvent_t>> g_prof_calls;  // events of unread calls
+std::vector<hipEvent_t> g_prof_pool;                 // recycled events
+}  // namespace
+
+hipEvent_t *profile_events() {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return nullptr;
+    std::vector<hipEvent_t> ev(kPhases + 1);
+    for (auto &e : ev) {
+        if (!g_prof_pool.empty()) {
+            e = g_prof_pool.back();
+            g_prof_pool.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            return nullptr;
+        }
+    }
+    g_prof_calls.push_back(std::move(ev));
+    return g_prof_calls.back().data();
+}
+int ensure_capture_arena();  // hk_batched.hip
+void release_batched();       // hk_batched.hip
+
+}  // namespace hk
+
+using namespace hk;
+
+extern "C" {
+
+int64_t hk_max_clusters(int32_t nx, int32_t ny, int32_t nz) {
+    if (nx < 1 || ny < 1 || nz < 1) return 0;
+    return ((int64_t)nx * ny * nz + 1) / 2;
+}
+
+int64_t hk_workspace_bytes(int32_t nx, int32_t ny, int32_t nz) {
+    const int rc = check_shape(nx, ny, nz, 0);
+    if (rc != HK_OK) return rc;
+    Geo g;
+    const int pr = plan_lattice(nx, ny, nz, 0, &g);
+    if (pr != HK_OK) return pr;
+    return layout_of(g, 0).total + kErrBytes;
+}
+
+int hk_label(const float *phi, int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask, int32_t *labels,
+             int64_t *n_clusters, int64_t *sizes, hipStream_t stream) {
+    if (!phi || !labels || !n_clusters) return HK_ERR_INVALID_ARG;
+    int rc = check_shape(nx, ny, nz, periodic_mask);
+    if (rc != HK_OK) return rc;
+    if ((const void *)labels == (const void *)phi) return HK_ERR_INVALID_ARG;
+    Geo g;
+    rc = plan_lattice(nx, ny, nz, periodic_mask, &g);
+    if (rc != HK_OK) return rc;
+    const Layout L = layout_of(g, 0);
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace *ws = nullptr;
+    rc = get_workspace(stream, L.total, &ws);
+    if (rc != HK_OK) return rc;
+    g.err = (int32_t *)ws->base;
+    bind(&g, ws->base + kErrBytes, L);
+    g.phi = phi;
+    g.labels = labels;
+    g.n_clusters = n_clusters;
+    g.sizes = sizes;
+    (void)hipGetLastError();
+    hipEvent_t *ev = profile_events();
+    if (launch_single(g, stream, ev) != hipSuccess) return HK_ERR_HIP;
+    return HK_OK;
+}
+
+int hk_reserve(int64_t bytes, hipStream_t stream) {
+    if (bytes < 0) return HK_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    Workspace *ws = nullptr;
+    const int rc = get_workspace(stream, bytes, &ws);
+    if (rc != HK_OK) return rc;
+    return ensure_capture_arena();
+}
+
+void hk_release(void) {
+    std::lock_guard<std::mutex> lk(g_ws_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto &kv : g_ws) {
+        if (!kv.second.base) continue;
+        (void)hipSetDevice(kv.first.first);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(kv.second.base);
+    }
+    g_ws.clear();
+    release_batched();
+    (void)hipSetDevice(cur);
+}
+
+const char *hk_status_string(int status) {
+    switch (status) {
+        case HK_OK: return "HK_OK";
+        case HK_ERR_INVALID_ARG: return "HK_ERR_INVALID_ARG: invalid argument";
+        case HK_ERR_TOO_LARGE: return "HK_ERR_TOO_LARGE: lattice too large";
+        case HK_ERR_NO_WORKSPACE: return "HK_ERR_NO_WORKSPACE: workspace must be reserved before capture";
+        case HK_ERR_HIP: return "HK_ERR_HIP: HIP runtime or launch failure";
+        case HK_ERR_DEVICE: return "HK_ERR_DEVICE: a device-side check fired";
+        default: return "unknown hk status";
+    }
+}
+
+int hk_set_brick(int32_t by, int32_t bz) {
+    if (by == 0 && bz == 0) {
+        std::lock_guard<std::mutex> lk(g_brick_mu);
+        g_force_by = g_force_bz = 0;
+        return HK_OK;
+    }
+    if (!is_pow2(by) || !is_pow2(bz) || by * bz > RMAX) return HK_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_brick_mu);
+    g_force_by = by;
+    g_force_bz = bz;
+    return HK_OK;
+}
+
+int hk_get_brick(int32_t nx, int32_t ny, int32_t nz, int32_t *by, int32_t *bz) {
+    if (!by || !bz) return HK_ERR_INVALID_ARG;
+    const int rc = check_shape(nx, ny, nz, 0);
+    if (rc != HK_OK) return rc;
+    Geo g;
+    const int pr = plan_lattice(nx, ny, nz, 0, &g);
+    if (pr != HK_OK) return pr;
+    *by = g.BY;
+    *bz = g.BZ;
+    return HK_OK;
+}
+
+int hk_set_brick_for_shape(int32_t nx, int32_t ny, int32_t nz, int32_t by, int32_t bz) {
+    const int rc = check_shape(nx, ny, nz, 0);
+    if (rc != HK_OK) return rc;
+    if (by == 0 && bz == 0) {
+        std::lock_guard<std::mutex> lk(g_brick_mu);
+        g_tuned.erase(bucket_of(nx, ny, nz));
+        return HK_OK;
+    }
+    if (!is_pow2(by) || !is_pow2(bz) || by * bz > RMAX) return HK_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_brick_mu);
+    g_tuned[bucket_of(nx, ny, nz)] = {by, bz};
+    return HK_OK;
+}
+
+int hk_profile_enable(int32_t enable) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = enable != 0;
+    return HK_OK;
+}
+
+int hk_profile_read(float *ms, int32_t n, int32_t *calls) {
+    if (!ms || n < 0) return HK_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (int i = 0; i < n; ++i) ms[i] = 0.0f;
+    const int32_t c = (int32_t)g_prof_calls.size();
+    int rc = HK_OK;
+    for (auto &ev : g_prof_calls) {
+        if (hipEventSynchronize(ev[kPhases]) != hipSuccess) rc = HK_ERR_HIP;
+        for (int i = 0; i < kPhases && i < n && rc == HK_OK; ++i) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) rc = HK_ERR_HIP;
+            ms[i] += t;
+        }
+        for (auto e : ev) g_prof_pool.push_back(e);
+    }
+    g_prof_calls.clear();
+    if (calls) *calls = c;
+    return rc;
+}
+
+int32_t hk_phase_count(void) { return kPhases; }
+
+const char *hk_phase_name(int32_t i) { return (i >= 0 && i < kPhases) ? kPhaseNames[i] : ""; }
+
+int hk_device_error(hipStream_t stream, int32_t *code) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HK_ERR_HIP;
+    int32_t v = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        auto it = g_ws.find({dev, stream});
+        if (it == g_ws.end() || !it->second.base) {
+            if (code) *code = 0;
+            return HK_OK;
+        }
+        if (hipStreamSynchronize(stream) != hipSuccess) return HK_ERR_HIP;
+        if (hipMemcpy(&v, it->second.base, sizeof(v), hipMemcpyDeviceToHost) != hipSuccess) return HK_ERR_HIP;
+        if (v != 0 && hipMemset(it->second.base, 0, sizeof(v)) != hipSuccess) return HK_ERR_HIP;
+    }
+    if (code) *code = v;
+    return v ? HK_ERR_DEVICE : HK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+"""The C-ABI library loads and exports every entry point include/hk.h
+declares; host-side argument checks and sizing work without a GPU."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1405_1931_amd import _lib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "hk.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(hk_[a-z_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libhk.so not built")
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 12
+    raw = ctypes.CDLL(_lib.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), f"{n} declared in hk.h but not exported"
+    # and the binding knows the signature of each
+    assert set(names) <= set(_lib._SIGS)
+
+
+def test_max_clusters(lib):
+    assert lib.hk_max_clusters(1, 1, 1) == 1
+    assert lib.hk_max_clusters(3, 5, 7) == 53
+    assert lib.hk_max_clusters(1024, 1024, 1024) == 2 ** 29
+    assert lib.hk_max_clusters(0, 5, 5) == 0
+
+
+def test_status_strings(lib):
+    for s in (0, -1, -2, -3, -4, -5):
+        assert lib.hk_status_string(s).startswith(b"HK_")
+    assert b"unknown" in lib.hk_status_string(42)
+
+
+def test_argument_errors_without_gpu(lib):
+    dummy = ctypes.c_void_p(0x1000)
+    # null pointers
+    assert lib.hk_label(None, 4, 4, 4, 0, dummy, dummy, None, None) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_label(dummy, 4, 4, 4, 0, None, dummy, None, None) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_label(dummy, 4, 4, 4, 0, dummy, None, None, None) == _lib.HK_ERR_INVALID_ARG
+    # bad edges and masks
+    for dims in [(0, 1, 1), (1, -2, 1), (1, 1, 0)]:
+        assert lib.hk_label(dummy, *dims, 0, ctypes.c_void_p(0x2000), dummy, None, None) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_label(dummy, 2, 2, 2, 8, ctypes.c_void_p(0x2000), dummy, None, None) == _lib.HK_ERR_INVALID_ARG
+    # labels aliasing phi
+    assert lib.hk_label(dummy, 2, 2, 2, 0, dummy, ctypes.c_void_p(0x3000), None, None) == _lib.HK_ERR_INVALID_ARG
+    # more than INT32_MAX sites
+    assert lib.hk_label(dummy, 2048, 2048, 1024, 0, ctypes.c_void_p(0x2000), dummy, None, None) == _lib.HK_ERR_TOO_LARGE
+    # batched: bad count / null table / one bad job rejects the whole call
+    assert lib.hk_label_batched(None, 3, None) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_label_batched(None, -1, None) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_label_batched(None, 0, None) == _lib.HK_OK
+    jobs = (_lib.HkJob * 2)()
+    jobs[0] = _lib.HkJob(0x1000, 4, 4, 4, 0, 0x2000, 0x3000, None)
+    jobs[1] = _lib.HkJob(0x1000, 4, 0, 4, 0, 0x2000, 0x3000, None)
+    assert lib.hk_label_batched(jobs, 2, None) == _lib.HK_ERR_INVALID_ARG
+
+
+def test_sizing_and_bricks(lib):
+    b = lib.hk_workspace_bytes(1024, 1024, 1024)
+    assert b > 0
+    assert lib.hk_workspace_bytes(0, 1, 1) == _lib.HK_ERR_INVALID_ARG
+    by, bz = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.hk_get_brick(1024, 1024, 1024, ctypes.byref(by), ctypes.byref(bz)) == 0
+    assert by.value * bz.value <= 256 and by.value > 0 and bz.value > 0
+    assert lib.hk_set_brick(3, 4) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_set_brick(32, 16) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_set_brick(8, 4) == 0
+    assert lib.hk_get_brick(100, 100, 100, ctypes.byref(by), ctypes.byref(bz)) == 0
+    assert (by.value, bz.value) == (8, 4)
+    assert lib.hk_set_brick(0, 0) == 0
+    assert lib.hk_set_brick_for_shape(200, 200, 200, 4, 4) == 0
+    assert lib.hk_get_brick(220, 250, 130, ctypes.byref(by), ctypes.byref(bz)) == 0
+    assert (by.value, bz.value) == (4, 4)
+    assert lib.hk_set_brick_for_shape(200, 200, 200, 0, 0) == 0
+    jobs = (_lib.HkJob * 3)()
+    for i, d in enumerate([(32, 40, 50), (64, 64, 64), (190, 33, 77)]):
+        jobs[i] = _lib.HkJob(None, *d, 0, None, None, None)
+    assert lib.hk_batched_workspace_bytes(jobs, 3) > 0
+    # thin lattices still get a plan
+    assert lib.hk_workspace_bytes(1, 1, 1 << 30) > 0
+    assert lib.hk_workspace_bytes(1 << 30, 1, 1) > 0
