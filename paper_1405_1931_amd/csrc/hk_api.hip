@@ -48,17 +48,20 @@ int64_t n_bricks(int nx, int ny, int nz, int by, int bz) {
     return (int64_t)((nx + 63) / 64) * ((ny + by - 1) / by) * ((nz + bz - 1) / bz);
 }
 
-void heuristic_brick(int nx, int ny, int nz, int *by, int *bz) {
+// Every brick costs a fixed latency, so bricks are as large as the lattice
+// allows; a lone small lattice trades some of that for more bricks in flight
+// (down to 64 x 8 x 8), while a lattice of a batch never does, since the
+// batch itself fills the chip.
+void heuristic_brick(int nx, int ny, int nz, bool batch, int *by, int *bz) {
     int y = std::min(16, ceil_pow2(ny)), z = std::min(16, ceil_pow2(nz));
-    // keep several bricks per compute unit while bricks stay reasonably big
-    while (n_bricks(nx, ny, nz, y, z) < 2048 && y * z > 16) {
+    while (!batch && n_bricks(nx, ny, nz, y, z) < 1024 && y * z > 64) {
         if (y >= z) y >>= 1; else z >>= 1;
     }
     *by = y;
     *bz = z;
 }
 
-void choose_brick(int nx, int ny, int nz, int *by, int *bz) {
+void choose_brick(int nx, int ny, int nz, bool batch, int *by, int *bz) {
     std::lock_guard<std::mutex> lk(g_brick_mu);
     if (g_force_by > 0) {
         *by = g_force_by;
@@ -71,13 +74,14 @@ void choose_brick(int nx, int ny, int nz, int *by, int *bz) {
         *bz = it->second.second;
         return;
     }
-    heuristic_brick(nx, ny, nz, by, bz);
+    heuristic_brick(nx, ny, nz, batch, by, bz);
 }
 
 // ---------------------------------------------------------------- plans
 
 struct Layout {
-    int64_t occ, root, wpre, face, bcount, npar, nkey, nsize, nlpos, rowcnt, blksum, total;
+    int64_t occ, root, wpre, face, bcount, npar, nkey, nsize, nlpos, nrootpos, runlab, icomp, icount, ncanon, nrun,
+        rowcnt, blksum, total;
 };
 
 // geometry (no pointers) of one lattice; false if it cannot be handled
@@ -103,6 +107,9 @@ bool make_geo(int nx, int ny, int nz, uint32_t mask, int by, int bz, Geo *g) {
     if (nb > INT32_MAX || nb * cap > INT32_MAX || nb * g->R > ((int64_t)1 << 40)) return false;
     g->nb = (int)nb;
     g->cap = (int)cap;
+    g->runcap = g->R * ((exm + 1) / 2);  // a row of exm sites holds <= ceil(exm/2) runs
+    g->icap = (int)c2;                   // components of a brick <= half its sites
+    if (nb * (int64_t)g->runcap > ((int64_t)1 << 40) || nb * (int64_t)g->icap > ((int64_t)1 << 40)) return false;
     g->fstride = 2 * g->R + 128 * bz + 128 * by;
     g->rows = ny * nz;
     g->nblk = (g->rows + WG - 1) / WG;
@@ -128,6 +135,12 @@ Layout layout_of(const Geo &g, int64_t base) {
     L.nkey = take(nodes * 4);
     L.nsize = take(nodes * 4);
     L.nlpos = take(nodes * 2);
+    L.nrootpos = take(nodes * 8);
+    L.runlab = take((int64_t)g.nb * g.runcap * 2);
+    L.icomp = take((int64_t)g.nb * g.icap * 4);
+    L.icount = take((int64_t)g.nb * 4);
+    L.ncanon = take(nodes * 4);
+    L.nrun = take((int64_t)g.nb * 4);
     L.rowcnt = take((int64_t)g.rows * 4);
     L.blksum = take((int64_t)g.nblk * 4);
     L.total = o - base;
@@ -144,6 +157,12 @@ void bind(Geo *g, char *base, const Layout &L) {
     g->nkey = (int32_t *)(base + L.nkey);
     g->nsize = (int32_t *)(base + L.nsize);
     g->nlpos = (uint16_t *)(base + L.nlpos);
+    g->nrootpos = (int64_t *)(base + L.nrootpos);
+    g->runlab = (uint16_t *)(base + L.runlab);
+    g->icomp = (uint32_t *)(base + L.icomp);
+    g->icount = (int32_t *)(base + L.icount);
+    g->ncanon = (int32_t *)(base + L.ncanon);
+    g->nrun = (int32_t *)(base + L.nrun);
     g->rowcnt = (int32_t *)(base + L.rowcnt);
     g->blksum = (int32_t *)(base + L.blksum);
 }
@@ -155,9 +174,9 @@ int check_shape(int32_t nx, int32_t ny, int32_t nz, uint32_t mask) {
 }
 
 // plan one lattice: geometry with a brick that fits
-int plan_lattice(int32_t nx, int32_t ny, int32_t nz, uint32_t mask, Geo *g) {
+int plan_lattice(int32_t nx, int32_t ny, int32_t nz, uint32_t mask, Geo *g, bool batch = false) {
     int by, bz;
-    choose_brick(nx, ny, nz, &by, &bz);
+    choose_brick(nx, ny, nz, batch, &by, &bz);
     if (make_geo(nx, ny, nz, mask, by, bz, g)) return HK_OK;
     // fall back to smaller bricks (fewer node slots per brick)
     for (int r = by * bz / 2; r >= 1; r /= 2) {
@@ -214,7 +233,7 @@ int get_workspace(hipStream_t stream, int64_t bytes, Workspace **out) {
 
 // exposed to the batched path
 int plan_lattice_ext(int32_t nx, int32_t ny, int32_t nz, uint32_t mask, Geo *g) {
-    return plan_lattice(nx, ny, nz, mask, g);
+    return plan_lattice(nx, ny, nz, mask, g, true);
 }
 int64_t lattice_bytes(const Geo &g) { return layout_of(g, 0).total; }
 void bind_lattice(Geo *g, char *base) { bind(g, base, layout_of(*g, 0)); }

@@ -4,16 +4,17 @@
 // consecutive x-sites of one (y, z)) is one 64-bit occupancy word, so runs of
 // occupied sites along x are bit runs and a wavefront ballot over 64 sites
 // produces a word directly.  Every phase below works on one brick (or one
-// block of 256 lattice rows) with a 256-thread workgroup; the single-lattice
-// kernels launch one workgroup per item, the batched persistent kernel pulls
-// the same items from a queue.
+// block of WG lattice rows) with a WG-thread workgroup; in the brick phases
+// four threads share a row, each owning a 16-bit slice of it.  The
+// single-lattice kernels launch one workgroup per item, the batched
+// persistent kernel pulls the same items from a queue.
 //
 // Phases (paper correspondence in brackets):
 //   pack    phi -> occupancy words                      [Sec. 2 condition]
-//   local   union-find of x-runs inside a brick (LDS):  [Sec. 2 rules 1-3,
+//   local   rules 2/3 on x-runs inside a brick (LDS):   [Sec. 2 rules 1-3,
 //           components that touch a face shared with     restricted to a brick]
 //           another brick (or a periodic wrap) become
-//           global nodes; the rest are final clusters
+//           global nodes; the rest are finished clusters
 //   merge   union of nodes across brick faces and       [Sec. 3 halo /
 //           periodic wraps, lock-free CAS linking         periodic equivalences]
 //           toward the node with the lowest site
@@ -21,9 +22,8 @@
 //           sizes at each root, mark root sites           to the lowest label]
 //   rowsum / scanblk / rowpre: prefix count of roots    [Sec. 2 compaction to
 //           over occupancy words in linear order          1..n]
-//   write   redo the brick labelling, map each          [Sec. 2 final pass,
-//           component to 1 + rank of its root,            Sec. 5 sizes]
-//           write labels and sizes
+//   write   component slot -> 1 + rank of its root,     [Sec. 2 final pass,
+//           sizes from the root, labels of all sites      Sec. 5 sizes]
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,9 +31,14 @@
 
 namespace hk {
 
-constexpr int WG = 256;               // threads per workgroup (4 wave64)
-constexpr int RMAX = 256;             // rows per brick at most (BY * BZ)
+constexpr int WG = 512;               // threads per workgroup (8 wave64)
+constexpr int NW = WG / 64;           // waves per workgroup
+constexpr int TPR = 2;                // threads per brick row
+constexpr int SLICE = 64 / TPR;       // bits of a row owned by one thread
+constexpr int RMAX = WG / TPR;        // rows per brick at most (BY * BZ)
 constexpr int MAXRUNS = 32 * RMAX;    // a 64-bit row holds at most 32 runs
+constexpr int LPOS_BITS = RMAX <= 256 ? 14 : 15;  // bits of a brick-local site position row*64+x
+static_assert(RMAX <= 512, "run ids, positions and sizes are packed for at most 512 rows");
 constexpr uint16_t NOSITE = 0xFFFF;   // face-table entry of an empty site
 constexpr int GUARD = 1 << 22;        // bound on any retry/walk loop
 
@@ -69,6 +74,14 @@ struct Geo {
     int32_t *nkey;    // [nb*cap] linear index of the node's lowest site
     int32_t *nsize;   // [nb*cap] sites in the node; at a root, the cluster
     uint16_t *nlpos;  // [nb*cap] brick-local position row*64 + x of the key
+    int64_t *nrootpos; // [nb*cap] word index << 6 | bit of the node's root key site
+    int32_t *ncanon;  // [nb*cap] final label of the node's cluster
+    int32_t *nrun;    // [nb] runs of each brick
+    uint16_t *runlab; // [nb][runcap] component slot of every run of the brick
+    uint32_t *icomp;  // [nb][icap] interior component: size << LPOS_BITS | key position
+    int32_t *icount;  // [nb] interior components of each brick
+    int32_t runcap;   // run slots per brick
+    int32_t icap;     // interior component slots per brick
     int32_t *rowcnt;  // [rows] roots per lattice row
     int32_t *blksum;  // [nblk] roots per block of rows, then their prefix
     int32_t *err;     // sticky check flag
@@ -88,10 +101,9 @@ struct __align__(16) LdsBrick {
     uint64_t occ[RMAX];
     uint64_t rootw[RMAX];
     int32_t rowoff[RMAX + 1];
-    int32_t broff[RMAX + 1];
     int32_t wpre[RMAX];
     uint32_t bflag[MAXRUNS / 32];
-    int32_t tmp[8];
+    int32_t tmp[32];
     int32_t par[MAXRUNS];
 };
 
@@ -116,6 +128,9 @@ __device__ __forceinline__ uint64_t mask_le(int b) { return b >= 63 ? ~0ull : ((
 // bits 0..b-1
 __device__ __forceinline__ uint64_t mask_lt(int b) { return b <= 0 ? 0ull : (b >= 64 ? ~0ull : ((1ull << b) - 1ull)); }
 
+// the SLICE bits of a row owned by slice q
+__device__ __forceinline__ uint64_t slice_bits(int q) { return (~0ull >> (64 - SLICE)) << (SLICE * q); }
+
 // length of the run of ones starting at bit s
 __device__ __forceinline__ int run_len(uint64_t w, int s) {
     const uint64_t x = ~(w >> s);
@@ -135,7 +150,7 @@ __device__ __forceinline__ void gl_st(int32_t *p, int v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// exclusive prefix sum over the 256 threads of the workgroup; all threads call
+// exclusive prefix sum over the WG threads of the workgroup; all threads call
 __device__ __forceinline__ int block_excl_scan(int v, int32_t *tmp, int *total) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int x = v;
@@ -146,10 +161,13 @@ __device__ __forceinline__ int block_excl_scan(int v, int32_t *tmp, int *total) 
     }
     if (lane == 63) tmp[w] = x;
     __syncthreads();
-    int base = 0;
+    int base = 0, tot = 0;
 #pragma unroll
-    for (int i = 0; i < WG / 64; ++i) base += (i < w) ? tmp[i] : 0;
-    const int tot = tmp[0] + tmp[1] + tmp[2] + tmp[3];
+    for (int i = 0; i < NW; ++i) {
+        const int p = tmp[i];
+        base += (i < w) ? p : 0;
+        tot += p;
+    }
     __syncthreads();
     *total = tot;
     return base + x - v;
@@ -229,16 +247,6 @@ __device__ __forceinline__ void l_unite(const Geo &g, int32_t *par, int a, int b
     set_err(g, ERR_LOOP);
 }
 
-// walk to the root without writing (used once no more links happen)
-__device__ __forceinline__ int l_root(int32_t *par, int x) {
-    for (int i = 0; i < GUARD; ++i) {
-        const int p = lds_ld(par + x);
-        if (p == x) return x;
-        x = p;
-    }
-    return x;
-}
-
 // --------------------------------------------------------------------------
 // union-find over global nodes: a root is linked (CAS) below the root whose
 // key (linear index of its lowest site) is smaller, so each cluster's final
@@ -268,25 +276,6 @@ __device__ __forceinline__ int g_find(const Geo &g, int x) {
     return x;
 }
 
-// walk to the root without writing: once no more links happen, each node's
-// own entry is then written by exactly one thread (a halving store from a
-// concurrent walk could otherwise overwrite a freshly flattened entry with
-// an intermediate ancestor)
-__device__ __forceinline__ int g_root(const Geo &g, int x) {
-    const int nn = n_nodes(g);
-    for (int i = 0; i < GUARD; ++i) {
-        const int p = gl_ld(g.npar + x);
-        if (p == x) return x;
-        if ((unsigned)p >= (unsigned)nn) {
-            set_err(g, ERR_RANGE);
-            return x;
-        }
-        x = p;
-    }
-    set_err(g, ERR_LOOP);
-    return x;
-}
-
 __device__ __forceinline__ void g_unite(const Geo &g, int a, int b) {
     const int nn = n_nodes(g);
     if ((unsigned)a >= (unsigned)nn || (unsigned)b >= (unsigned)nn) {
@@ -308,24 +297,26 @@ __device__ __forceinline__ void g_unite(const Geo &g, int a, int b) {
 }
 
 // --------------------------------------------------------------------------
-// phase: pack phi into occupancy words (one workgroup per brick)
+// phase: pack phi into occupancy words (one workgroup per brick); each wave
+// takes a band of rows, lane j keeps the ballot of the band's j-th row
 // --------------------------------------------------------------------------
 
 __device__ __forceinline__ void phase_pack(const Geo &g, int b) {
     const Brick k = brick_of(g, b);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int rpw = (g.R + NW - 1) / NW;
     constexpr int U = 16;
-    for (int base = wv * 64; base < g.R; base += WG) {
+    for (int base = wv * rpw; base < min(g.R, (wv + 1) * rpw); base += 64) {
+        const int end = min(min(g.R, (wv + 1) * rpw), base + 64);
         uint64_t mine = 0;
-#pragma unroll
-        for (int j0 = 0; j0 < 64; j0 += U) {
+        for (int j0 = 0; j0 < 64 && base + j0 < end; j0 += U) {
             float v[U];
 #pragma unroll
             for (int j = 0; j < U; ++j) {
                 const int r = base + j0 + j;
                 const int yl = r & (g.BY - 1), zl = r >> g.lby;
                 v[j] = 0.0f;
-                if (r < g.R && yl < k.ey && zl < k.ez && lane < k.ex)
+                if (r < end && yl < k.ey && zl < k.ez && lane < k.ex)
                     v[j] = g.phi[((int64_t)(k.z0 + zl) * g.ny + (k.y0 + yl)) * g.nx + k.x0 + lane];
             }
 #pragma unroll
@@ -334,81 +325,155 @@ __device__ __forceinline__ void phase_pack(const Geo &g, int b) {
                 if (lane == j0 + j) mine = m;
             }
         }
-        if (base + lane < g.R) g.occ[(int64_t)b * g.R + base + lane] = mine;
+        if (base + lane < end) g.occ[(int64_t)b * g.R + base + lane] = mine;
     }
 }
 
 // --------------------------------------------------------------------------
-// brick-local labelling shared by the local and write phases
+// brick-local labelling (local phase)
 //   in : s.occ[0..R)
-//   out: s.rowoff, s.par (non-root run -> root run; root run -> -1 - size),
-//        s.bflag (root runs touching a shared face), s.broff (prefix of such
-//        roots per row, in run order)
+//   out: s.rowoff; s.par: non-root run -> root run, root run -> -1 - size;
+//        s.bflag: root runs touching a shared face; per thread, the number of
+//        roots and boundary roots before the runs of its slice
 // --------------------------------------------------------------------------
 
-__device__ __forceinline__ void unite_rows(const Geo &g, LdsBrick &s, int r, int rp, uint64_t w, uint64_t st) {
+__device__ __forceinline__ bool bflag_get(const LdsBrick &s, int id) { return (s.bflag[id >> 5] >> (id & 31)) & 1u; }
+__device__ __forceinline__ void bflag_set(LdsBrick &s, int id) { atomicOr(&s.bflag[id >> 5], 1u << (id & 31)); }
+
+// The serial pass's rules, applied to the overlap segments of a row with its
+// predecessor row rp that start in slice q: the first overlapping run of rp
+// to claim a run becomes its parent (rule 2, the label of the single labelled
+// neighbour); every further overlap is an equivalence (rule 3), stored after
+// the live runs in the par array as (a << 16 | b) while room lasts.
+__device__ __forceinline__ void link_rows(LdsBrick &s, int rp, uint64_t w, uint64_t st, int offr, int q, int nruns) {
     const uint64_t wp = s.occ[rp];
     const uint64_t o = w & wp;
-    uint64_t seg = o & ~(o << 1);
-    if (!seg) return;
+    uint64_t seg = o & ~(o << 1) & slice_bits(q);
     const uint64_t stp = run_starts(wp);
-    const int offr = s.rowoff[r], offp = s.rowoff[rp];
+    const int offp = s.rowoff[rp];
     while (seg) {
         const int bb = __builtin_ctzll(seg);
         seg &= seg - 1;
         const uint64_t mk = mask_le(bb);
         const int a = offr + __popcll(st & mk) - 1;
         const int c = offp + __popcll(stp & mk) - 1;
-        l_unite(g, s.par, a, c);
+        if (atomicCAS(s.par + a, a, c) != a) {
+            const int e = atomicAdd(&s.tmp[20], 1);
+            if (nruns + e < MAXRUNS) s.par[nruns + e] = (a << 16) | c;
+        }
     }
 }
 
-__device__ __forceinline__ bool bflag_get(const LdsBrick &s, int id) { return (s.bflag[id >> 5] >> (id & 31)) & 1u; }
-__device__ __forceinline__ void bflag_set(LdsBrick &s, int id) { atomicOr(&s.bflag[id >> 5], 1u << (id & 31)); }
+// union of every overlap segment of the row with rp in slice q (fallback)
+__device__ __forceinline__ void unite_rows(const Geo &g, LdsBrick &s, int rp, uint64_t w, uint64_t st, int offr, int q) {
+    const uint64_t wp = s.occ[rp];
+    const uint64_t o = w & wp;
+    uint64_t seg = o & ~(o << 1) & slice_bits(q);
+    const uint64_t stp = run_starts(wp);
+    const int offp = s.rowoff[rp];
+    while (seg) {
+        const int bb = __builtin_ctzll(seg);
+        seg &= seg - 1;
+        const uint64_t mk = mask_le(bb);
+        l_unite(g, s.par, offr + __popcll(st & mk) - 1, offp + __popcll(stp & mk) - 1);
+    }
+}
 
-__device__ __forceinline__ void brick_core(const Geo &g, const Brick &k, LdsBrick &s) {
-    const int t = threadIdx.x;
+// pointer jumping: par[x] <- par[par[x]] over all runs until every entry is
+// a root; each entry is written only by its own thread, so concurrent reads
+// always see an ancestor
+__device__ __forceinline__ void jump_flatten(LdsBrick &s, int nruns) {
+    for (int round = 0; round < 64; ++round) {
+        int changed = 0;
+        for (int x = threadIdx.x; x < nruns; x += WG) {
+            const int p = lds_ld(s.par + x);
+            const int gp = lds_ld(s.par + p);
+            if (gp != p) {
+                lds_st(s.par + x, gp);
+                changed = 1;
+            }
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+}
+
+struct CoreOut {
+    int nruns;   // runs in the brick
+    int roots;   // components of the brick
+    int broots;  // components touching a shared face
+    int cpre;    // components whose root run precedes this thread's slice
+    int bpre;    // boundary components likewise
+};
+
+__device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsBrick &s) {
+    const int t = threadIdx.x, row = t / TPR, q = t % TPR;
     const int R = g.R;
-    const uint64_t w = (t < R) ? s.occ[t] : 0ull;
+    const bool live = row < R;
+    const uint64_t w = live ? s.occ[row] : 0ull;
     const uint64_t st = run_starts(w);
-    const int nr = __popcll(st);
+    const uint64_t mine = st & slice_bits(q);  // run starts owned by this thread
     int total;
-    const int off = block_excl_scan(nr, s.tmp, &total);
-    if (t < R) s.rowoff[t] = off;
-    if (t == 0) s.rowoff[R] = total;
-    s.bflag[t] = 0u;  // MAXRUNS / 32 == WG
-    for (int j = 0; j < nr; ++j) s.par[off + j] = off + j;
+    const int off = block_excl_scan(q == 0 ? __popcll(st) : 0, s.tmp, &total);
+    if (live && q == 0) s.rowoff[row] = off;
+    if (t == 0) {
+        s.rowoff[R] = total;
+        s.tmp[20] = 0;  // equivalence count
+    }
+    if (t < MAXRUNS / 32) s.bflag[t] = 0u;
+    __syncthreads();
+    const int offr = live ? s.rowoff[row] : 0;
+    // runs of this slice: ids first .. first + count - 1
+    const int first = offr + __popcll(st & mask_lt(SLICE * q));
+    const int cnt = __popcll(mine);
+    for (int j = 0; j < cnt; ++j) s.par[first + j] = first + j;
     __syncthreads();
 
-    // rules 2/3 inside the brick: runs overlapping in the row below (y-1)
-    // and the plane below (z-1) are the same component
-    const int yl = t & (g.BY - 1), zl = t >> g.lby;
-    if (t < R && w) {
-        if (yl > 0) unite_rows(g, s, t, t - 1, w, st);
-        if (zl > 0) unite_rows(g, s, t, t - g.BY, w, st);
+    // rules 2/3 inside the brick against the row below (y-1) and the plane
+    // below (z-1); runs of different rows only meet there
+    const int yl = row & (g.BY - 1), zl = row >> g.lby;
+    if (live && w) {
+        if (yl > 0) link_rows(s, row - 1, w, st, offr, q, total);
+        if (zl > 0) link_rows(s, row - g.BY, w, st, offr, q, total);
     }
     __syncthreads();
+    const int ne = s.tmp[20];
+    jump_flatten(s, total);
 
-    for (int j = 0; j < nr; ++j) s.par[off + j] = l_root(s.par, off + j);
+    // equivalences: union of the (now flat) trees, linking toward the
+    // smaller run, so each component's root is its first run
+    const int stored = min(ne, MAXRUNS - total);
+    for (int e = t; e < stored; e += WG) {
+        const int v = s.par[total + e];
+        l_unite(g, s.par, v >> 16, v & 0xFFFF);
+    }
     __syncthreads();
+    if (stored < ne) {
+        // no room for every equivalence: unite all overlaps again (idempotent)
+        if (live && w) {
+            if (yl > 0) unite_rows(g, s, row - 1, w, st, offr, q);
+            if (zl > 0) unite_rows(g, s, row - g.BY, w, st, offr, q);
+        }
+        __syncthreads();
+    }
+    jump_flatten(s, total);
 
     // components touching a face shared with another brick (or a wrap)
-    if (t < R && w) {
+    if (live && w) {
         const bool frow = (k.hyl && yl == 0) || (k.hyh && yl == k.ey - 1) || (k.hzl && zl == 0) ||
                           (k.hzh && zl == k.ez - 1);
         if (frow) {
-            for (int j = 0; j < nr; ++j) bflag_set(s, s.par[off + j]);
-        } else {
-            if (k.hxl && (w & 1ull)) bflag_set(s, s.par[off]);
-            if (k.hxh && ((w >> (k.ex - 1)) & 1ull)) bflag_set(s, s.par[off + nr - 1]);
+            for (int j = 0; j < cnt; ++j) bflag_set(s, s.par[first + j]);
+        } else if (q == 0) {
+            if (k.hxl && (w & 1ull)) bflag_set(s, s.par[offr]);
+            if (k.hxh && ((w >> (k.ex - 1)) & 1ull)) bflag_set(s, s.par[offr + __popcll(st) - 1]);
         }
     }
     __syncthreads();
 
     // component sizes, accumulated in the root entry as -1 - size
     {
-        uint64_t m = st;
-        int id = off;
+        uint64_t m = mine;
+        int id = first;
         while (m) {
             const int sb = __builtin_ctzll(m);
             m &= m - 1;
@@ -418,8 +483,8 @@ __device__ __forceinline__ void brick_core(const Geo &g, const Brick &k, LdsBric
     }
     __syncthreads();
     {
-        uint64_t m = st;
-        int id = off;
+        uint64_t m = mine;
+        int id = first;
         while (m) {
             const int sb = __builtin_ctzll(m);
             m &= m - 1;
@@ -430,16 +495,21 @@ __device__ __forceinline__ void brick_core(const Geo &g, const Brick &k, LdsBric
     }
     __syncthreads();
 
-    int bc = 0;
-    for (int j = 0; j < nr; ++j) {
-        const int id = off + j;
-        bc += (s.par[id] < 0 && bflag_get(s, id)) ? 1 : 0;
+    // per slice: roots (high half) and boundary roots (low half), < 2^15 each
+    int c = 0;
+    for (int j = 0; j < cnt; ++j) {
+        const int id = first + j;
+        if (s.par[id] < 0) c += (1 << 16) + (bflag_get(s, id) ? 1 : 0);
     }
-    int btot;
-    const int boff = block_excl_scan(bc, s.tmp, &btot);
-    if (t < R) s.broff[t] = boff;
-    if (t == 0) s.broff[R] = btot;
-    __syncthreads();
+    int tot;
+    const int pre = block_excl_scan(c, s.tmp, &tot);
+    CoreOut out;
+    out.nruns = total;
+    out.roots = tot >> 16;
+    out.broots = tot & 0xFFFF;
+    out.cpre = pre >> 16;
+    out.bpre = pre & 0xFFFF;
+    return out;
 }
 
 // root run of a run after brick_core (root runs hold negative values)
@@ -449,60 +519,95 @@ __device__ __forceinline__ int root_of(const LdsBrick &s, int run) {
 }
 
 // --------------------------------------------------------------------------
-// phase: local -- label the brick, create its nodes and face tables
+// phase: local -- label the brick, create its nodes, its interior component
+// table, the component slot of every run and the face tables
 // --------------------------------------------------------------------------
 
 __device__ __forceinline__ void phase_local(const Geo &g, int b, LdsBrick &s) {
     const Brick k = brick_of(g, b);
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, row = t / TPR, q = t % TPR;
     const int R = g.R;
-    if (t < R) s.occ[t] = g.occ[(int64_t)b * R + t];
-    __syncthreads();
-    brick_core(g, k, s);
-
     if (t < R) {
-        const uint64_t w = s.occ[t];
-        uint64_t m = run_starts(w);
-        int id = s.rowoff[t];
-        int bi = s.broff[t];
-        const int yl = t & (g.BY - 1), zl = t >> g.lby;
+        s.occ[t] = g.occ[(int64_t)b * R + t];
+        s.rootw[t] = 0ull;
+    }
+    __syncthreads();
+    const CoreOut co = brick_core(g, k, s);
+
+    // component slots: boundary components take 0..B-1 (their node slots),
+    // interior components B..C-1; each root run's entry becomes -1 - slot
+    const int btot = co.broots;
+    if (row < R) {
+        const uint64_t w = s.occ[row];
+        const uint64_t st = run_starts(w);
+        uint64_t m = st & slice_bits(q);
+        int id = s.rowoff[row] + __popcll(st & mask_lt(SLICE * q));
+        int bi = co.bpre;
+        int ii = co.cpre - co.bpre;
+        const int yl = row & (g.BY - 1), zl = row >> g.lby;
         uint64_t rw = 0;
         while (m) {
             const int sb = __builtin_ctzll(m);
             m &= m - 1;
             const int v = s.par[id];
             if (v < 0) {
+                int c;
                 if (bflag_get(s, id)) {
-                    const int bidx = bi++;
-                    if (bidx < g.cap) {
-                        const int n = b * g.cap + bidx;
+                    c = bi++;
+                    if (c < g.cap) {
+                        const int n = b * g.cap + c;
                         g.nkey[n] = (k.x0 + sb) + g.nx * ((k.y0 + yl) + g.ny * (k.z0 + zl));
-                        g.nlpos[n] = (uint16_t)(t * 64 + sb);
+                        g.nlpos[n] = (uint16_t)(row * 64 + sb);
                         g.nsize[n] = -1 - v;
                         g.npar[n] = n;
                     } else {
                         set_err(g, ERR_CAP);
                     }
-                    s.par[id] = -1 - bidx;
                 } else {
-                    rw |= 1ull << sb;  // interior component: a finished cluster
+                    // interior component: a finished cluster, key and size kept
+                    rw |= 1ull << sb;
+                    if (ii < g.icap)
+                        g.icomp[(int64_t)b * g.icap + ii] = ((uint32_t)(-1 - v) << LPOS_BITS) | (uint32_t)(row * 64 + sb);
+                    else
+                        set_err(g, ERR_CAP);
+                    c = btot + ii++;
                 }
+                s.par[id] = -1 - c;
             }
             ++id;
         }
-        g.root[(int64_t)b * R + t] = rw;
+        if (rw) atomicOr((unsigned long long *)&s.rootw[row], (unsigned long long)rw);
     }
-    if (t == 0) g.bcount[b] = min(s.broff[R], g.cap);
+    if (t == 0) {
+        g.bcount[b] = min(btot, g.cap);
+        g.icount[b] = min(co.roots - btot, g.icap);
+        g.nrun[b] = min(co.nruns, g.runcap);
+    }
     __syncthreads();
+    if (t < R) g.root[(int64_t)b * R + t] = s.rootw[t];
+
+    // component slot of every run, for the final pass
+    uint16_t *L = g.runlab + (int64_t)b * g.runcap;
+    for (int id = t; id < co.nruns && id < g.runcap; id += WG) L[id] = (uint16_t)(-1 - s.par[root_of(s, id)]);
 
     uint16_t *F = g.face + (int64_t)b * g.fstride;
+    // y and z face rows, spread over the waves: entry f < ez is row (0, f)
+    // of the low y face, then the high y face, the low z face, the high z face
     const int lane = t & 63, wv = t >> 6;
-    for (int r = wv; r < R; r += WG / 64) {
-        const int yl = r & (g.BY - 1), zl = r >> g.lby;
-        if (yl >= k.ey || zl >= k.ez) continue;
-        const bool fyl = k.hyl && yl == 0, fyh = k.hyh && yl == k.ey - 1;
-        const bool fzl = k.hzl && zl == 0, fzh = k.hzh && zl == k.ez - 1;
-        if (!(fyl || fyh || fzl || fzh)) continue;
+    for (int f = wv; f < 2 * (k.ey + k.ez); f += NW) {
+        int yl, zl, sec;
+        bool on;
+        if (f < k.ez) {
+            yl = 0, zl = f, sec = f_ylo(g) + zl * 64, on = k.hyl;
+        } else if (f < 2 * k.ez) {
+            yl = k.ey - 1, zl = f - k.ez, sec = f_yhi(g) + zl * 64, on = k.hyh;
+        } else if (f < 2 * k.ez + k.ey) {
+            yl = f - 2 * k.ez, zl = 0, sec = f_zlo(g) + yl * 64, on = k.hzl;
+        } else {
+            yl = f - 2 * k.ez - k.ey, zl = k.ez - 1, sec = f_zhi(g) + yl * 64, on = k.hzh;
+        }
+        if (!on) continue;
+        const int r = yl + g.BY * zl;
         const uint64_t w = s.occ[r];
         uint16_t e = NOSITE;
         if ((w >> lane) & 1ull) {
@@ -513,10 +618,7 @@ __device__ __forceinline__ void phase_local(const Geo &g, int b, LdsBrick &s) {
             else
                 set_err(g, ERR_FACE);
         }
-        if (fyl) F[f_ylo(g) + zl * 64 + lane] = e;
-        if (fyh) F[f_yhi(g) + zl * 64 + lane] = e;
-        if (fzl) F[f_zlo(g) + yl * 64 + lane] = e;
-        if (fzh) F[f_zhi(g) + yl * 64 + lane] = e;
+        F[sec + lane] = e;
     }
     if (t < R) {
         const int yl = t & (g.BY - 1), zl = t >> g.lby;
@@ -550,13 +652,13 @@ __device__ __forceinline__ void phase_local(const Geo &g, int b, LdsBrick &s) {
 
 __device__ __forceinline__ void phase_merge(const Geo &g, int b) {
     const Brick k = brick_of(g, b);
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, nt = blockDim.x;
     const int R = g.R;
     const uint16_t *F = g.face + (int64_t)b * g.fstride;
     if (k.hxl) {
         const int nbb = k.bx > 0 ? b - 1 : b + (g.nbx - 1);
         const uint16_t *G = g.face + (int64_t)nbb * g.fstride;
-        for (int r = t; r < R; r += WG) {
+        for (int r = t; r < R; r += nt) {
             const int yl = r & (g.BY - 1), zl = r >> g.lby;
             if (yl >= k.ey || zl >= k.ez) continue;
             const uint16_t a = F[f_xlo(g) + r], c = G[f_xhi(g) + r];
@@ -568,7 +670,7 @@ __device__ __forceinline__ void phase_merge(const Geo &g, int b) {
     if (k.hyl) {
         const int nbb = k.by > 0 ? b - g.nbx : b + (g.nby - 1) * g.nbx;
         const uint16_t *G = g.face + (int64_t)nbb * g.fstride;
-        for (int e = t; e < 64 * k.ez; e += WG) {
+        for (int e = t; e < 64 * k.ez; e += nt) {
             const int x = e & 63;
             if (x >= k.ex) continue;
             const uint16_t a = F[f_ylo(g) + e], c = G[f_yhi(g) + e];
@@ -580,7 +682,7 @@ __device__ __forceinline__ void phase_merge(const Geo &g, int b) {
     if (k.hzl) {
         const int nbb = k.bz > 0 ? b - g.nbx * g.nby : b + (g.nbz - 1) * g.nbx * g.nby;
         const uint16_t *G = g.face + (int64_t)nbb * g.fstride;
-        for (int e = t; e < 64 * k.ey; e += WG) {
+        for (int e = t; e < 64 * k.ey; e += nt) {
             const int x = e & 63;
             if (x >= k.ex) continue;
             const uint16_t a = F[f_zlo(g) + e], c = G[f_zhi(g) + e];
@@ -592,25 +694,62 @@ __device__ __forceinline__ void phase_merge(const Geo &g, int b) {
 }
 
 // --------------------------------------------------------------------------
-// phase: roots -- flatten every node of the brick to its root; roots mark
-// their key site in the root bitmap, other nodes add their size to the root
+// phase: roots -- find the root of every node of the brick; roots mark their
+// key site in the root bitmap, every node records where its root's key site
+// is, and non-roots add their size to the root.
+//
+// Sizes of clusters that span many bricks (the spanning cluster spans all of
+// them) are first summed per brick in an LDS hash keyed by root node, then
+// added to the root with one global atomic per (brick, root), instead of one
+// per node.  Finds halve paths here; the node's parent entry itself is never
+// finalised (a concurrent halving store could overwrite it): the root
+// position is kept in its own array, written only by the node's thread.
 // --------------------------------------------------------------------------
 
-__device__ __forceinline__ void phase_roots(const Geo &g, int b) {
+constexpr int HT_BITS = 11;
+constexpr int HT = 1 << HT_BITS;  // hash slots: keys in hash[0, HT), sums in hash[HT, 2 HT)
+static_assert(2 * HT <= MAXRUNS, "the hash must fit in the run array of LdsBrick");
+
+__device__ __forceinline__ void phase_roots(const Geo &g, int b, int32_t *hash) {
+    int32_t *hkey = hash, *hval = hash + HT;
+    const int nt = blockDim.x;
+    for (int i = threadIdx.x; i < HT; i += nt) {
+        hkey[i] = -1;
+        hval[i] = 0;
+    }
+    __syncthreads();
     const int cnt = g.bcount[b];
-    for (int i = threadIdx.x; i < cnt; i += WG) {
+    for (int i = threadIdx.x; i < cnt; i += nt) {
         const int n = b * g.cap + i;
-        const int r = g_root(g, n);
+        const int r = g_find(g, n);
+        // position of the root's key site: word index << 6 | bit
+        const int lr = g.nlpos[r];
+        g.nrootpos[n] = (((int64_t)(r / g.cap) * g.R + min(lr >> 6, g.R - 1)) << 6) | (lr & 63);
         if (r == n) {
-            const int lp = g.nlpos[n];
-            if ((lp >> 6) < g.R)
-                atomicOr((unsigned long long *)(g.root + (int64_t)b * g.R + (lp >> 6)), 1ull << (lp & 63));
+            if ((lr >> 6) < g.R)
+                atomicOr((unsigned long long *)(g.root + (int64_t)b * g.R + (lr >> 6)), 1ull << (lr & 63));
             else
                 set_err(g, ERR_RANGE);
         } else {
-            gl_st(g.npar + n, r);
-            atomicAdd(g.nsize + r, g.nsize[n]);
+            const int add = g.nsize[n];
+            int h = (int)(((uint32_t)r * 2654435761u) >> (32 - HT_BITS));
+            bool done = false;
+            for (int probe = 0; probe < 64; ++probe) {
+                const int old = atomicCAS(hkey + h, -1, r);
+                if (old == -1 || old == r) {
+                    atomicAdd(hval + h, add);
+                    done = true;
+                    break;
+                }
+                h = (h + 1) & (HT - 1);
+            }
+            if (!done) atomicAdd(g.nsize + r, add);
         }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < HT; i += nt) {
+        const int r = hkey[i];
+        if (r >= 0) atomicAdd(g.nsize + r, hval[i]);
     }
 }
 
@@ -667,78 +806,95 @@ __device__ __forceinline__ void phase_rowpre(const Geo &g, int blk, int32_t *tmp
 }
 
 // --------------------------------------------------------------------------
-// phase: write -- redo the brick labelling, label = 1 + rank of the cluster's
-// root site among all root sites in linear order; sizes from the root
+// phase: canon -- final label of every node: 1 + rank of its cluster's root
+// site among all root sites in linear order (root bit words and per-word
+// prefixes); the root node also writes its cluster's size
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ void phase_canon(const Geo &g, int b) {
+    const int cnt = g.bcount[b];
+    const int64_t kmax = (n_sites(g) + 1) / 2;
+    const int64_t words = (int64_t)g.nb * g.R;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        const int n = b * g.cap + i;
+        const int64_t pos = g.nrootpos[n];
+        const int64_t wi = pos >> 6;
+        if (wi < 0 || wi >= words) {
+            set_err(g, ERR_RANGE);
+            continue;
+        }
+        const int rank = g.wpre[wi] + __popcll(g.root[wi] & mask_lt((int)(pos & 63)));
+        g.ncanon[n] = rank + 1;
+        const int lp = g.nlpos[n];
+        // this node holds the cluster's key site: it is the root
+        if (g.sizes && wi == (int64_t)b * g.R + min(lp >> 6, g.R - 1) && (pos & 63) == (lp & 63)) {
+            if (rank >= 0 && (int64_t)rank < kmax)
+                g.sizes[rank] = g.nsize[n];
+            else
+                set_err(g, ERR_RANGE);
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// phase: write -- label of every component slot of the brick (node label for
+// boundary slots, 1 + rank of the key site for interior ones, whose sizes
+// are written here); then every site takes the label of its run's slot.
+// All global inputs are requested before the first wait: slot labels and
+// raw interior entries go to s.par[0, nc), run slots to s.par[nc, nc + nr)
+// when they fit (else they are read from global memory per site).
 // --------------------------------------------------------------------------
 
 __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
     const Brick k = brick_of(g, b);
     const int t = threadIdx.x;
     const int R = g.R;
+    const int bc = g.bcount[b], nc = bc + g.icount[b], nr = g.nrun[b];
+    const bool fit = nc + nr <= MAXRUNS;
+    const uint16_t *L = g.runlab + (int64_t)b * g.runcap;
+    uint64_t w = 0;
     if (t < R) {
         const int64_t i = (int64_t)b * R + t;
-        s.occ[t] = g.occ[i];
+        w = g.occ[i];
+        s.occ[t] = w;
         s.rootw[t] = g.root[i];
         s.wpre[t] = g.wpre[i];
     }
-    __syncthreads();
-    brick_core(g, k, s);
+    for (int c = t; c < nc && c < MAXRUNS; c += WG)
+        s.par[c] = c < bc ? g.ncanon[(int64_t)b * g.cap + c] : (int32_t)g.icomp[(int64_t)b * g.icap + (c - bc)];
+    if (fit)
+        for (int id = t; id < nr; id += WG) s.par[nc + id] = L[id];
+    int nruns;
+    const int off = block_excl_scan(__popcll(run_starts(w)), s.tmp, &nruns);
+    if (t < R) s.rowoff[t] = off;
 
-    if (t < R) {
-        const uint64_t w = s.occ[t];
-        uint64_t m = run_starts(w);
-        int id = s.rowoff[t];
-        int bi = s.broff[t];
-        while (m) {
-            const int sb = __builtin_ctzll(m);
-            m &= m - 1;
-            const int v = s.par[id];
-            if (v < 0) {
-                int rank;
-                int64_t size = -1;
-                if (bflag_get(s, id)) {
-                    const int bidx = bi++;
-                    const int n = b * g.cap + min(bidx, g.cap - 1);
-                    int rn = g.npar[n];
-                    if ((unsigned)rn >= (unsigned)n_nodes(g)) {
-                        set_err(g, ERR_RANGE);
-                        rn = n;
-                    }
-                    if (rn == n) {
-                        rank = s.wpre[t] + __popcll(s.rootw[t] & mask_lt(sb));
-                        size = g.nsize[n];
-                    } else {
-                        const int bp = rn / g.cap;
-                        const int lp = g.nlpos[rn];
-                        const int64_t wi = (int64_t)bp * R + min(lp >> 6, R - 1);
-                        rank = g.wpre[wi] + __popcll(g.root[wi] & mask_lt(lp & 63));
-                    }
-                } else {
-                    rank = s.wpre[t] + __popcll(s.rootw[t] & mask_lt(sb));
-                    size = -1 - v;
-                }
-                if (size >= 0 && g.sizes) {
-                    if (rank >= 0 && (int64_t)rank < (n_sites(g) + 1) / 2)
-                        g.sizes[rank] = size;
-                    else
-                        set_err(g, ERR_RANGE);
-                }
-                s.par[id] = -(rank + 1);
-            }
-            ++id;
+    // interior slots: rank of the key site from this brick's own words
+    const int64_t kmax = (n_sites(g) + 1) / 2;
+    for (int c = bc + t; c < nc && c < MAXRUNS; c += WG) {
+        const uint32_t u = (uint32_t)s.par[c];
+        const int lp = (int)(u & ((1u << LPOS_BITS) - 1u));
+        const int r = min(lp >> 6, R - 1);
+        const int rank = s.wpre[r] + __popcll(s.rootw[r] & mask_lt(lp & 63));
+        if (g.sizes) {
+            if (rank >= 0 && (int64_t)rank < kmax)
+                g.sizes[rank] = (int64_t)(u >> LPOS_BITS);
+            else
+                set_err(g, ERR_RANGE);
         }
+        s.par[c] = rank + 1;
     }
     __syncthreads();
 
     const int lane = t & 63, wv = t >> 6;
-    for (int r = wv; r < R; r += WG / 64) {
+    for (int r = wv; r < R; r += NW) {
         const int yl = r & (g.BY - 1), zl = r >> g.lby;
         if (yl >= k.ey || zl >= k.ez) continue;
-        const uint64_t w = s.occ[r];
+        const uint64_t wr = s.occ[r];
         int lab = 0;
-        if ((w >> lane) & 1ull) {
-            const int run = s.rowoff[r] + __popcll(run_starts(w) & mask_le(lane)) - 1;
-            lab = -s.par[root_of(s, run)];
+        if ((wr >> lane) & 1ull) {
+            const int run = min(s.rowoff[r] + __popcll(run_starts(wr) & mask_le(lane)) - 1, g.runcap - 1);
+            const int slot = fit ? s.par[nc + run] : L[run];
+            lab = s.par[min(slot, MAXRUNS - 1)];
         }
         if (lane < k.ex) g.labels[((int64_t)(k.z0 + zl) * g.ny + (k.y0 + yl)) * g.nx + k.x0 + lane] = lab;
     }
@@ -755,7 +911,7 @@ __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
 // instead of hanging.
 // --------------------------------------------------------------------------
 
-constexpr int NPH = 8;  // pack, local, merge, roots, rowsum, scanblk, rowpre, write
+constexpr int NPH = 9;  // pack, local, merge, roots, rowsum, scanblk, rowpre, canon, write
 
 struct BatchView {
     const Geo *jobs;
@@ -799,18 +955,22 @@ __device__ __forceinline__ void persistent_loop(const BatchView &v, LdsBrick &s,
         const int i = rel - uni(off[j]);
         const Geo &g = v.jobs[j];
         if (p > 0) {
-            // every wave polls the counter as a scalar loop
-            const int32_t *prev = v.itoff + (p - 1) * (v.njobs + 1);
-            const int need = uni(prev[j + 1]) - uni(prev[j]);
-            int32_t *cnt = v.done + j * NPH + (p - 1);
-            const uint64_t t0 = wall_clock64();
-            for (;;) {
-                const int c = uni(__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-                if (c >= need) break;
-                __builtin_amdgcn_s_sleep(2);
-                if (wall_clock64() - t0 > v.wait_ticks) {
-                    atomicOr(v.err, one ? ERR_LOOP : 0);
-                    break;
+            // wave 0 polls the counter as a scalar loop, the others wait at
+            // the barrier (one poller per workgroup keeps the counters' L2
+            // channel free for the work itself)
+            if (wave == 0) {
+                const int32_t *prev = v.itoff + (p - 1) * (v.njobs + 1);
+                const int need = uni(prev[j + 1]) - uni(prev[j]);
+                int32_t *cnt = v.done + j * NPH + (p - 1);
+                const uint64_t t0 = wall_clock64();
+                for (;;) {
+                    const int c = uni(__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+                    if (c >= need) break;
+                    __builtin_amdgcn_s_sleep(8);
+                    if (wall_clock64() - t0 > v.wait_ticks) {
+                        atomicOr(v.err, one ? ERR_LOOP : 0);
+                        break;
+                    }
                 }
             }
             __syncthreads();
@@ -820,10 +980,11 @@ __device__ __forceinline__ void persistent_loop(const BatchView &v, LdsBrick &s,
             case 0: phase_pack(g, i); break;
             case 1: phase_local(g, i, s); break;
             case 2: phase_merge(g, i); break;
-            case 3: phase_roots(g, i); break;
+            case 3: phase_roots(g, i, s.par); break;
             case 4: phase_rowsum(g, i, s.tmp); break;
             case 5: phase_scanblk(g, s.tmp); break;
             case 6: phase_rowpre(g, i, s.tmp); break;
+            case 7: phase_canon(g, i); break;
             default: phase_write(g, i, s); break;
         }
         __threadfence();

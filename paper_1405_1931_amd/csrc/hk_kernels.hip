@@ -1,5 +1,5 @@
 // Kernels of the single-lattice path: one workgroup per brick (or per block
-// of 256 lattice rows) and one launch per phase, all on the caller's stream.
+// of WG lattice rows) and one launch per phase, all on the caller's stream.
 #include "hk_device.h"
 #include "hk_launch.h"
 
@@ -12,35 +12,44 @@ __global__ __launch_bounds__(WG) void k_local(Geo g) {
     phase_local(g, blockIdx.x, s);
 }
 
-__global__ __launch_bounds__(WG) void k_merge(Geo g) { phase_merge(g, blockIdx.x); }
+// the node phases (global union-find, node labels) are latency bound and
+// carry little work per brick: small workgroups keep many bricks in flight
+constexpr int WG_NODES = 256;
 
-__global__ __launch_bounds__(WG) void k_roots(Geo g) { phase_roots(g, blockIdx.x); }
+__global__ __launch_bounds__(WG_NODES) void k_merge(Geo g) { phase_merge(g, blockIdx.x); }
+
+__global__ __launch_bounds__(WG_NODES) void k_roots(Geo g) {
+    __shared__ int32_t hash[2 * HT];
+    phase_roots(g, blockIdx.x, hash);
+}
 
 __global__ __launch_bounds__(WG) void k_rowsum(Geo g) {
-    __shared__ int32_t tmp[8];
+    __shared__ int32_t tmp[32];
     phase_rowsum(g, blockIdx.x, tmp);
 }
 
 __global__ __launch_bounds__(WG) void k_scanblk(Geo g) {
-    __shared__ int32_t tmp[8];
+    __shared__ int32_t tmp[32];
     phase_scanblk(g, tmp);
 }
 
 __global__ __launch_bounds__(WG) void k_rowpre(Geo g) {
-    __shared__ int32_t tmp[8];
+    __shared__ int32_t tmp[32];
     phase_rowpre(g, blockIdx.x, tmp);
 }
+
+__global__ __launch_bounds__(WG_NODES) void k_canon(Geo g) { phase_canon(g, blockIdx.x); }
 
 __global__ __launch_bounds__(WG) void k_write(Geo g) {
     __shared__ LdsBrick s;
     phase_write(g, blockIdx.x, s);
 }
 
-const char *const kPhaseNames[kPhases] = {"k_pack", "k_local", "k_merge", "k_roots",
-                                          "k_rowsum", "k_scanblk", "k_rowpre", "k_write"};
+const char *const kPhaseNames[kPhases] = {"k_pack",   "k_local",  "k_merge", "k_roots", "k_rowsum",
+                                          "k_scanblk", "k_rowpre", "k_canon", "k_write"};
 
 hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev) {
-    const dim3 blk(WG);
+    const dim3 blk(WG), small(WG_NODES);
     auto mark = [&](int i) {
         if (ev) (void)hipEventRecord(ev[i], st);
     };
@@ -49,9 +58,9 @@ hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev) {
     mark(1);
     hipLaunchKernelGGL(k_local, dim3(g.nb), blk, 0, st, g);
     mark(2);
-    hipLaunchKernelGGL(k_merge, dim3(g.nb), blk, 0, st, g);
+    hipLaunchKernelGGL(k_merge, dim3(g.nb), small, 0, st, g);
     mark(3);
-    hipLaunchKernelGGL(k_roots, dim3(g.nb), blk, 0, st, g);
+    hipLaunchKernelGGL(k_roots, dim3(g.nb), small, 0, st, g);
     mark(4);
     hipLaunchKernelGGL(k_rowsum, dim3(g.nblk), blk, 0, st, g);
     mark(5);
@@ -59,8 +68,10 @@ hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev) {
     mark(6);
     hipLaunchKernelGGL(k_rowpre, dim3(g.nblk), blk, 0, st, g);
     mark(7);
-    hipLaunchKernelGGL(k_write, dim3(g.nb), blk, 0, st, g);
+    hipLaunchKernelGGL(k_canon, dim3(g.nb), small, 0, st, g);
     mark(8);
+    hipLaunchKernelGGL(k_write, dim3(g.nb), blk, 0, st, g);
+    mark(9);
     return hipGetLastError();
 }
 
