@@ -107,7 +107,9 @@ bool make_geo(int nx, int ny, int nz, uint32_t mask, int by, int bz, Geo *g) {
     if (nb > INT32_MAX || nb * cap > INT32_MAX || nb * g->R > ((int64_t)1 << 40)) return false;
     g->nb = (int)nb;
     g->cap = (int)cap;
-    g->runcap = g->R * ((exm + 1) / 2);  // a row of exm sites holds <= ceil(exm/2) runs
+    // a row of exm sites holds <= ceil(exm/2) runs; a multiple of four keeps
+    // every brick's run table 8-byte aligned for the relabel pass
+    g->runcap = (g->R * ((exm + 1) / 2) + 3) & ~3;
     g->icap = (int)c2;                   // components of a brick <= half its sites
     if (nb * (int64_t)g->runcap > ((int64_t)1 << 40) || nb * (int64_t)g->icap > ((int64_t)1 << 40)) return false;
     g->fstride = 2 * g->R + 128 * bz + 128 * by;

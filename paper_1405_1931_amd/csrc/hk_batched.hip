@@ -265,7 +265,7 @@ int hk_label_batched(const hk_job *jobs, int32_t n_jobs, hipStream_t stream) {
     }
 
     BatchView v;
-    v.jobs = (const Geo *)(table + tl.jobs);
+    v.jobs = (ConstGeo *)(table + tl.jobs);
     v.itoff = (const int32_t *)(table + tl.itoff);
     v.pstart = (const int32_t *)(table + tl.pstart);
     v.done = (int32_t *)(table + tl.done);

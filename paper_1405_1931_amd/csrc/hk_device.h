@@ -845,6 +845,30 @@ __device__ __forceinline__ void phase_canon(const Geo &g, int b) {
 // when they fit (else they are read from global memory per site).
 // --------------------------------------------------------------------------
 
+// Expand run labels to sites, one lattice row per wave and one site per
+// lane.  The two forms are kept apart so that the common one (run table in
+// LDS) has no global load in its loop: loads and stores share one
+// outstanding-memory counter, and a load in the loop body makes every row
+// wait for all earlier label stores to drain.
+template <bool RUNS_IN_LDS>
+__device__ __forceinline__ void write_rows(const Geo &g, const Brick &k, const LdsBrick &s, int nc,
+                                           const uint16_t *L) {
+    const int t = threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
+    for (int r = wv; r < g.R; r += NW) {
+        const int yl = r & (g.BY - 1), zl = r >> g.lby;
+        if (yl >= k.ey || zl >= k.ez) continue;
+        const uint64_t wr = s.occ[r];
+        int lab = 0;
+        if ((wr >> lane) & 1ull) {
+            const int run = min(s.rowoff[r] + __popcll(run_starts(wr) & mask_le(lane)) - 1, g.runcap - 1);
+            const int slot = RUNS_IN_LDS ? s.par[nc + run] : L[run];
+            lab = s.par[min(slot, MAXRUNS - 1)];
+        }
+        if (lane < k.ex) g.labels[((int64_t)(k.z0 + zl) * g.ny + (k.y0 + yl)) * g.nx + k.x0 + lane] = lab;
+    }
+}
+
 __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
     const Brick k = brick_of(g, b);
     const int t = threadIdx.x;
@@ -860,10 +884,41 @@ __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
         s.rootw[t] = g.root[i];
         s.wpre[t] = g.wpre[i];
     }
-    for (int c = t; c < nc && c < MAXRUNS; c += WG)
-        s.par[c] = c < bc ? g.ncanon[(int64_t)b * g.cap + c] : (int32_t)g.icomp[(int64_t)b * g.icap + (c - bc)];
-    if (fit)
-        for (int id = t; id < nr; id += WG) s.par[nc + id] = L[id];
+    // Every load of the preamble is issued before the first wait: slot
+    // labels (boundary, then interior) and, when they fit, the run slots four
+    // to a 64-bit word (runcap is a multiple of four).
+    {
+        const int ncl = min(nc, MAXRUNS);
+        for (int c0 = t; c0 < ncl; c0 += 4 * WG) {
+            int32_t v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int c = c0 + u * WG;
+                v[u] = c >= ncl ? 0
+                       : c < bc ? g.ncanon[(int64_t)b * g.cap + c]
+                                : (int32_t)g.icomp[(int64_t)b * g.icap + (c - bc)];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (c0 + u * WG < ncl) s.par[c0 + u * WG] = v[u];
+        }
+        if (fit) {
+            const uint64_t *L4 = reinterpret_cast<const uint64_t *>(L);
+            const int nq = (nr + 3) >> 2;
+            for (int q0 = t; q0 < nq; q0 += 4 * WG) {
+                uint64_t v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] = q0 + u * WG < nq ? L4[q0 + u * WG] : 0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int id = 4 * (q0 + u * WG);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (id + j < nr) s.par[nc + id + j] = (int32_t)((v[u] >> (16 * j)) & 0xffffu);
+                }
+            }
+        }
+    }
     int nruns;
     const int off = block_excl_scan(__popcll(run_starts(w)), s.tmp, &nruns);
     if (t < R) s.rowoff[t] = off;
@@ -885,19 +940,10 @@ __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
     }
     __syncthreads();
 
-    const int lane = t & 63, wv = t >> 6;
-    for (int r = wv; r < R; r += NW) {
-        const int yl = r & (g.BY - 1), zl = r >> g.lby;
-        if (yl >= k.ey || zl >= k.ez) continue;
-        const uint64_t wr = s.occ[r];
-        int lab = 0;
-        if ((wr >> lane) & 1ull) {
-            const int run = min(s.rowoff[r] + __popcll(run_starts(wr) & mask_le(lane)) - 1, g.runcap - 1);
-            const int slot = fit ? s.par[nc + run] : L[run];
-            lab = s.par[min(slot, MAXRUNS - 1)];
-        }
-        if (lane < k.ex) g.labels[((int64_t)(k.z0 + zl) * g.ny + (k.y0 + yl)) * g.nx + k.x0 + lane] = lab;
-    }
+    if (fit)
+        write_rows<true>(g, k, s, nc, L);
+    else
+        write_rows<false>(g, k, s, nc, L);
 }
 
 // --------------------------------------------------------------------------
@@ -913,8 +959,14 @@ __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
 
 constexpr int NPH = 9;  // pack, local, merge, roots, rowsum, scanblk, rowpre, canon, write
 
+// The job table is written before the launch and never during it: it is read
+// through the constant address space, so the compiler may keep or re-fetch
+// its fields with scalar loads instead of treating every store of a phase as
+// a possible write to them.
+typedef const __attribute__((address_space(4))) Geo ConstGeo;
+
 struct BatchView {
-    const Geo *jobs;
+    ConstGeo *jobs;
     const int32_t *itoff;   // [NPH][njobs + 1] item offsets of each job within a phase
     const int32_t *pstart;  // [NPH + 1] first item of each phase
     int32_t *done;          // [njobs][NPH] finished items
@@ -953,7 +1005,7 @@ __device__ __forceinline__ void persistent_loop(const BatchView &v, LdsBrick &s,
         }
         const int j = lo;
         const int i = rel - uni(off[j]);
-        const Geo &g = v.jobs[j];
+        const Geo &g = *(const Geo *)(v.jobs + j);
         if (p > 0) {
             // wave 0 polls the counter as a scalar loop, the others wait at
             // the barrier (one poller per workgroup keeps the counters' L2
