@@ -1,20 +1,19 @@
-// Batched labelling: many lattices of any shapes in ONE persistent launch.
+// Batched labelling: many lattices of any shapes in one stream-ordered
+// group of launches.
 //
-// Work items are (phase, job, item) triples laid out phase-major: all pack
-// items of every job, then all local items, ... then all write items.
-// Resident workgroups pop item indices from a global counter.  Before an
-// item of phase p runs, the workgroup waits until every item of phase p-1 of
-// the same job has finished (per-job, per-phase completion counters).  An
-// item only ever waits for items with smaller indices, which were popped
-// earlier by workgroups that are already running, so the queue always drains
-// (the oldest unfinished item never waits).  Every wait is also bounded by a
-// wall-clock limit that sets the sticky device error instead of hanging.
+// Each phase of the path is ONE kernel over the items (bricks, blocks of
+// rows) of every job of the batch: workgroup w of phase p runs item
+// w - itoff[p][j] of the job j whose item range holds w.  The phases of a job
+// depend on each other only through the kernel boundaries, where the device
+// makes every write of one phase visible to the next.  (A single persistent
+// launch with per-item completion counters needs a device-scope release and
+// acquire around every item; with one L2 per XCD those are L2 write-backs
+// and invalidations, which cost more than the items themselves.)
 //
-// The job table (per-job geometry and workspace pointers, item offsets,
-// zeroed counters) is uploaded with one host-to-device copy from pinned
-// memory right before the launch, so a hipGraph capture of one call holds
-// exactly one copy node and one kernel node, and every replay starts from
-// zeroed counters.
+// The job table (per-job geometry and workspace pointers, per-phase item
+// offsets) is uploaded with one host-to-device copy from pinned memory right
+// before the launches, so a hipGraph capture of one call holds one copy node
+// and one kernel node per phase.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -25,14 +24,71 @@
 
 #include "../../include/hk.h"
 #include "hk_device.h"
+#include "hk_launch.h"
 
 namespace hk {
 
-__global__ __launch_bounds__(WG) void k_batched(BatchView v) {
-    __shared__ LdsBrick s;
-    __shared__ int s_item;
-    persistent_loop(v, s, s_item);
+__global__ __launch_bounds__(WG) void kb_pack(GroupView v) {
+    int i;
+    const Geo &g = locate(v, 0, blockIdx.x, &i);
+    phase_pack(g, i);
 }
+
+__global__ __launch_bounds__(WG) void kb_local(GroupView v) {
+    __shared__ LdsBrick s;
+    int i;
+    const Geo &g = locate(v, 1, blockIdx.x, &i);
+    phase_local(g, i, s);
+}
+
+__global__ __launch_bounds__(WG_NODES) void kb_merge(GroupView v) {
+    int i;
+    const Geo &g = locate(v, 2, blockIdx.x, &i);
+    phase_merge(g, i);
+}
+
+__global__ __launch_bounds__(WG_NODES) void kb_roots(GroupView v) {
+    __shared__ int32_t hash[2 * HT];
+    int i;
+    const Geo &g = locate(v, 3, blockIdx.x, &i);
+    phase_roots(g, i, hash);
+}
+
+__global__ __launch_bounds__(WG) void kb_rowsum(GroupView v) {
+    __shared__ int32_t tmp[32];
+    int i;
+    const Geo &g = locate(v, 4, blockIdx.x, &i);
+    phase_rowsum(g, i, tmp);
+}
+
+__global__ __launch_bounds__(WG) void kb_scanblk(GroupView v) {
+    __shared__ int32_t tmp[32];
+    int i;
+    const Geo &g = locate(v, 5, blockIdx.x, &i);
+    phase_scanblk(g, tmp);
+}
+
+__global__ __launch_bounds__(WG) void kb_rowpre(GroupView v) {
+    __shared__ int32_t tmp[32];
+    int i;
+    const Geo &g = locate(v, 6, blockIdx.x, &i);
+    phase_rowpre(g, i, tmp);
+}
+
+__global__ __launch_bounds__(WG_NODES) void kb_canon(GroupView v) {
+    int i;
+    const Geo &g = locate(v, 7, blockIdx.x, &i);
+    phase_canon(g, i);
+}
+
+__global__ __launch_bounds__(WG) void kb_write(GroupView v) {
+    __shared__ LdsBrick s;
+    int i;
+    const Geo &g = locate(v, 8, blockIdx.x, &i);
+    phase_write(g, i, s);
+}
+
+static_assert(NPH == kPhases, "one grouped kernel per phase of the single-lattice path");
 
 // ------------------------------------------------------------------- host
 
@@ -46,22 +102,8 @@ namespace {
 
 int64_t al(int64_t v) { return (v + 255) / 256 * 256; }
 
-// bound on one dependency wait inside the persistent kernel: HK_WAIT_MS
-// milliseconds (default 10 s), in ticks of the 100 MHz constant clock
-uint64_t wait_ticks() {
-    static uint64_t ticks = [] {
-        uint64_t ms = 10000;
-        if (const char *e = std::getenv("HK_WAIT_MS")) {
-            const long v = std::atol(e);
-            if (v > 0) ms = (uint64_t)v;
-        }
-        return ms * 100000ull;
-    }();
-    return ticks;
-}
-
 struct TableLayout {
-    int64_t jobs, itoff, pstart, done, next, total;
+    int64_t jobs, itoff, total;
 };
 
 TableLayout table_layout(int n) {
@@ -71,12 +113,6 @@ TableLayout table_layout(int n) {
     o = al(o + (int64_t)n * sizeof(Geo));
     t.itoff = o;
     o = al(o + (int64_t)NPH * (n + 1) * 4);
-    t.pstart = o;
-    o = al(o + (NPH + 1) * 4);
-    t.done = o;
-    o = al(o + (int64_t)n * NPH * 4);
-    t.next = o;
-    o = al(o + 4);
     t.total = o;
     return t;
 }
@@ -110,8 +146,7 @@ int validate_and_plan(const hk_job *jobs, int n, bool need_ptrs, std::vector<Geo
 }
 
 // pinned staging blocks for the job table: a small ring reused once the copy
-// that last read a block has completed; blocks used under capture are kept
-// for the lifetime of the library (a graph replays from them)
+// that last read a block has completed
 struct Staging {
     void *host[4] = {nullptr, nullptr, nullptr, nullptr};
     int64_t cap[4] = {0, 0, 0, 0};
@@ -131,17 +166,38 @@ struct CaptureArena {
 CaptureArena g_arena;
 constexpr int64_t kArenaBytes = 8ll << 20;
 
-int grid_size() {
-    static int cached[64] = {0};
+// upload the table image to `table` on `stream` from pinned memory
+int upload_table(const std::vector<char> &img, char *table, hipStream_t stream) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return HK_ERR_HIP;
+    const int64_t n = (int64_t)img.size();
+    if (cs != hipStreamCaptureStatusNone) {
+        if (!g_arena.base || g_arena.used + al(n) > g_arena.size) return HK_ERR_NO_WORKSPACE;
+        char *host = g_arena.base + g_arena.used;
+        g_arena.used += al(n);
+        std::memcpy(host, img.data(), (size_t)n);
+        return hipMemcpyAsync(table, host, (size_t)n, hipMemcpyHostToDevice, stream) == hipSuccess ? HK_OK
+                                                                                                   : HK_ERR_HIP;
+    }
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (dev >= 0 && dev < 64 && cached[dev]) return cached[dev];
-    int per_cu = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batched, WG, 0) != hipSuccess) per_cu = 1;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 1;
-    const int v = std::max(1, per_cu) * std::max(1, cus);
-    if (dev >= 0 && dev < 64) cached[dev] = v;
-    return v;
+    (void)hipGetDevice(&dev);
+    Staging &sg = g_stage[{dev, stream}];
+    const int k = sg.next;
+    sg.next = (k + 1) % 4;
+    if (sg.used[k] && hipEventSynchronize(sg.ev[k]) != hipSuccess) return HK_ERR_HIP;
+    if (sg.cap[k] < n) {
+        if (sg.host[k]) (void)hipHostFree(sg.host[k]);
+        sg.host[k] = nullptr;
+        sg.cap[k] = 0;
+        if (hipHostMalloc(&sg.host[k], (size_t)n, hipHostMallocDefault) != hipSuccess) return HK_ERR_HIP;
+        sg.cap[k] = n;
+    }
+    if (!sg.ev[k] && hipEventCreateWithFlags(&sg.ev[k], hipEventDisableTiming) != hipSuccess) return HK_ERR_HIP;
+    std::memcpy(sg.host[k], img.data(), (size_t)n);
+    if (hipMemcpyAsync(table, sg.host[k], (size_t)n, hipMemcpyHostToDevice, stream) != hipSuccess) return HK_ERR_HIP;
+    if (hipEventRecord(sg.ev[k], stream) != hipSuccess) return HK_ERR_HIP;
+    sg.used[k] = true;
+    return HK_OK;
 }
 
 }  // namespace
@@ -193,7 +249,23 @@ int hk_label_batched(const hk_job *jobs, int32_t n_jobs, hipStream_t stream) {
     int rc = validate_and_plan(jobs, n_jobs, true, &geos, &bytes);
     if (rc != HK_OK) return rc;
 
+    // item offsets of every job within every phase
     const TableLayout tl = table_layout(n_jobs);
+    std::vector<char> img((size_t)tl.total, 0);
+    int32_t *itoff = (int32_t *)(img.data() + tl.itoff);
+    int64_t items[NPH];
+    for (int p = 0; p < NPH; ++p) {
+        int32_t *off = itoff + p * (n_jobs + 1);
+        int64_t acc = 0;
+        for (int j = 0; j < n_jobs; ++j) {
+            off[j] = (int32_t)acc;
+            acc += items_of(geos[j], p);
+            if (acc > INT32_MAX) return HK_ERR_TOO_LARGE;
+        }
+        off[n_jobs] = (int32_t)acc;
+        items[p] = acc;
+    }
+
     std::lock_guard<std::mutex> lk(workspace_mutex());
     char *base = nullptr;
     int32_t *err = nullptr;
@@ -201,26 +273,7 @@ int hk_label_batched(const hk_job *jobs, int32_t n_jobs, hipStream_t stream) {
     if (rc != HK_OK) return rc;
     char *table = base;
     char *cursor = base + tl.total;
-
-    // host image of the table
-    std::vector<char> img((size_t)tl.total, 0);
     Geo *hj = (Geo *)(img.data() + tl.jobs);
-    int32_t *itoff = (int32_t *)(img.data() + tl.itoff);
-    int32_t *pstart = (int32_t *)(img.data() + tl.pstart);
-    int64_t items = 0;
-    for (int p = 0; p < NPH; ++p) {
-        pstart[p] = (int32_t)items;
-        int32_t *off = itoff + p * (n_jobs + 1);
-        int32_t acc = 0;
-        for (int j = 0; j < n_jobs; ++j) {
-            off[j] = acc;
-            acc += items_of(geos[j], p);
-        }
-        off[n_jobs] = acc;
-        items += acc;
-        if (items > INT32_MAX / 2) return HK_ERR_TOO_LARGE;
-    }
-    pstart[NPH] = (int32_t)items;
     for (int j = 0; j < n_jobs; ++j) {
         Geo g = geos[j];
         bind_lattice(&g, cursor);
@@ -232,51 +285,24 @@ int hk_label_batched(const hk_job *jobs, int32_t n_jobs, hipStream_t stream) {
         g.sizes = jobs[j].sizes;
         hj[j] = g;
     }
+    rc = upload_table(img, table, stream);
+    if (rc != HK_OK) return rc;
 
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(stream, &cs) != hipSuccess) return HK_ERR_HIP;
-    if (cs != hipStreamCaptureStatusNone) {
-        if (!g_arena.base || g_arena.used + tl.total > g_arena.size) return HK_ERR_NO_WORKSPACE;
-        char *host = g_arena.base + g_arena.used;
-        g_arena.used += tl.total;
-        std::memcpy(host, img.data(), img.size());
-        if (hipMemcpyAsync(table, host, (size_t)tl.total, hipMemcpyHostToDevice, stream) != hipSuccess)
-            return HK_ERR_HIP;
-    } else {
-        int dev = 0;
-        (void)hipGetDevice(&dev);
-        Staging &sg = g_stage[{dev, stream}];
-        const int k = sg.next;
-        sg.next = (k + 1) % 4;
-        if (sg.used[k] && hipEventSynchronize(sg.ev[k]) != hipSuccess) return HK_ERR_HIP;
-        if (sg.cap[k] < tl.total) {
-            if (sg.host[k]) (void)hipHostFree(sg.host[k]);
-            sg.host[k] = nullptr;
-            sg.cap[k] = 0;
-            if (hipHostMalloc(&sg.host[k], (size_t)tl.total, hipHostMallocDefault) != hipSuccess) return HK_ERR_HIP;
-            sg.cap[k] = tl.total;
-        }
-        if (!sg.ev[k] && hipEventCreateWithFlags(&sg.ev[k], hipEventDisableTiming) != hipSuccess) return HK_ERR_HIP;
-        std::memcpy(sg.host[k], img.data(), img.size());
-        if (hipMemcpyAsync(table, sg.host[k], (size_t)tl.total, hipMemcpyHostToDevice, stream) != hipSuccess)
-            return HK_ERR_HIP;
-        if (hipEventRecord(sg.ev[k], stream) != hipSuccess) return HK_ERR_HIP;
-        sg.used[k] = true;
-    }
-
-    BatchView v;
+    GroupView v;
     v.jobs = (ConstGeo *)(table + tl.jobs);
-    v.itoff = (const int32_t *)(table + tl.itoff);
-    v.pstart = (const int32_t *)(table + tl.pstart);
-    v.done = (int32_t *)(table + tl.done);
-    v.next = (int32_t *)(table + tl.next);
-    v.err = err;
+    v.itoff = (ConstI32 *)(table + tl.itoff);
     v.njobs = n_jobs;
-    v.total = (int32_t)items;
-    v.wait_ticks = wait_ticks();
-    const int grid = std::max(1, std::min<int>(grid_size(), (int)items));
+    const dim3 blk(WG), small(WG_NODES);
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_batched, dim3(grid), dim3(WG), 0, stream, v);
+    hipLaunchKernelGGL(kb_pack, dim3((unsigned)items[0]), blk, 0, stream, v);
+    hipLaunchKernelGGL(kb_local, dim3((unsigned)items[1]), blk, 0, stream, v);
+    hipLaunchKernelGGL(kb_merge, dim3((unsigned)items[2]), small, 0, stream, v);
+    hipLaunchKernelGGL(kb_roots, dim3((unsigned)items[3]), small, 0, stream, v);
+    hipLaunchKernelGGL(kb_rowsum, dim3((unsigned)items[4]), blk, 0, stream, v);
+    hipLaunchKernelGGL(kb_scanblk, dim3((unsigned)items[5]), blk, 0, stream, v);
+    hipLaunchKernelGGL(kb_rowpre, dim3((unsigned)items[6]), blk, 0, stream, v);
+    hipLaunchKernelGGL(kb_canon, dim3((unsigned)items[7]), small, 0, stream, v);
+    hipLaunchKernelGGL(kb_write, dim3((unsigned)items[8]), blk, 0, stream, v);
     if (hipGetLastError() != hipSuccess) return HK_ERR_HIP;
     return HK_OK;
 }

@@ -5,9 +5,9 @@
 // occupied sites along x are bit runs and a wavefront ballot over 64 sites
 // produces a word directly.  Every phase below works on one brick (or one
 // block of WG lattice rows) with a WG-thread workgroup; in the brick phases
-// four threads share a row, each owning a 16-bit slice of it.  The
-// single-lattice kernels launch one workgroup per item, the batched
-// persistent kernel pulls the same items from a queue.
+// TPR threads share a row, each owning a SLICE-bit slice of it.  The
+// single-lattice kernels launch one workgroup per item; the batched kernels
+// launch one workgroup per item of every job of a batch.
 //
 // Phases (paper correspondence in brackets):
 //   pack    phi -> occupancy words                      [Sec. 2 condition]
@@ -39,6 +39,9 @@ constexpr int RMAX = WG / TPR;        // rows per brick at most (BY * BZ)
 constexpr int MAXRUNS = 32 * RMAX;    // a 64-bit row holds at most 32 runs
 constexpr int LPOS_BITS = RMAX <= 256 ? 14 : 15;  // bits of a brick-local site position row*64+x
 static_assert(RMAX <= 512, "run ids, positions and sizes are packed for at most 512 rows");
+// the node phases (global union-find, node labels) are latency bound and
+// carry little work per brick: small workgroups keep many bricks in flight
+constexpr int WG_NODES = 256;
 constexpr uint16_t NOSITE = 0xFFFF;   // face-table entry of an empty site
 constexpr int GUARD = 1 << 22;        // bound on any retry/walk loop
 
@@ -947,103 +950,36 @@ __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
 }
 
 // --------------------------------------------------------------------------
-// batched persistent loop: work items are (phase, job, item) triples laid
-// out phase-major; a workgroup pops the next index, waits until every item
-// of the previous phase of the same job has finished, runs the item, then
-// publishes its completion.  An item only waits for items with smaller
-// indices, popped earlier by workgroups that are already running, so the
-// oldest unfinished item never waits and the queue always drains.  Every
-// wait is bounded by a wall-clock limit that sets the sticky device error
-// instead of hanging.
+// batched launches: one kernel per phase covers the items of every job of
+// the batch; workgroup w finds its job by a search over the per-phase item
+// offsets.  The job table is written before the launches and never during
+// them, so it is read through the constant address space: the compiler may
+// keep or re-fetch its fields with scalar loads instead of treating every
+// store of a phase as a possible write to them.
 // --------------------------------------------------------------------------
 
 constexpr int NPH = 9;  // pack, local, merge, roots, rowsum, scanblk, rowpre, canon, write
 
-// The job table is written before the launch and never during it: it is read
-// through the constant address space, so the compiler may keep or re-fetch
-// its fields with scalar loads instead of treating every store of a phase as
-// a possible write to them.
 typedef const __attribute__((address_space(4))) Geo ConstGeo;
+typedef const __attribute__((address_space(4))) int32_t ConstI32;
 
-struct BatchView {
+struct GroupView {
     ConstGeo *jobs;
-    const int32_t *itoff;   // [NPH][njobs + 1] item offsets of each job within a phase
-    const int32_t *pstart;  // [NPH + 1] first item of each phase
-    int32_t *done;          // [njobs][NPH] finished items
-    int32_t *next;          // queue head
-    int32_t *err;
+    ConstI32 *itoff;  // [NPH][njobs + 1] first item of each job within a phase
     int32_t njobs;
-    int32_t total;
-    uint64_t wait_ticks;    // bound on one wait, in ticks of the 100 MHz clock
 };
 
-// Control flow of the loop is kept wave-uniform everywhere a barrier can
-// follow: the queue and counter atomics are issued by the whole of wave 0
-// with a non-zero operand in lane 0 only, and every value that steers a
-// branch is broadcast with readfirstlane.  (A single-lane `if` around them
-// let the compiler structure the loop exit as divergent, and waves then
-// drifted apart across barriers.)
-__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
-
-__device__ __forceinline__ void persistent_loop(const BatchView &v, LdsBrick &s, int &s_item) {
-    const int wave = uni(threadIdx.x >> 6);
-    const int one = (threadIdx.x & 63) == 0 ? 1 : 0;
-    for (;;) {
-        if (wave == 0) s_item = uni(atomicAdd(v.next, one));
-        __syncthreads();
-        const int it = uni(s_item);
-        __syncthreads();
-        if (it >= v.total) break;
-        int p = 0;
-        while (p < NPH - 1 && it >= uni(v.pstart[p + 1])) ++p;
-        const int rel = it - uni(v.pstart[p]);
-        const int32_t *off = v.itoff + p * (v.njobs + 1);
-        int lo = 0, hi = v.njobs;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (uni(off[mid]) <= rel) lo = mid; else hi = mid;
-        }
-        const int j = lo;
-        const int i = rel - uni(off[j]);
-        const Geo &g = *(const Geo *)(v.jobs + j);
-        if (p > 0) {
-            // wave 0 polls the counter as a scalar loop, the others wait at
-            // the barrier (one poller per workgroup keeps the counters' L2
-            // channel free for the work itself)
-            if (wave == 0) {
-                const int32_t *prev = v.itoff + (p - 1) * (v.njobs + 1);
-                const int need = uni(prev[j + 1]) - uni(prev[j]);
-                int32_t *cnt = v.done + j * NPH + (p - 1);
-                const uint64_t t0 = wall_clock64();
-                for (;;) {
-                    const int c = uni(__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-                    if (c >= need) break;
-                    __builtin_amdgcn_s_sleep(8);
-                    if (wall_clock64() - t0 > v.wait_ticks) {
-                        atomicOr(v.err, one ? ERR_LOOP : 0);
-                        break;
-                    }
-                }
-            }
-            __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
-        switch (p) {
-            case 0: phase_pack(g, i); break;
-            case 1: phase_local(g, i, s); break;
-            case 2: phase_merge(g, i); break;
-            case 3: phase_roots(g, i, s.par); break;
-            case 4: phase_rowsum(g, i, s.tmp); break;
-            case 5: phase_scanblk(g, s.tmp); break;
-            case 6: phase_rowpre(g, i, s.tmp); break;
-            case 7: phase_canon(g, i); break;
-            default: phase_write(g, i, s); break;
-        }
-        __threadfence();
-        __syncthreads();
-        if (wave == 0)
-            __hip_atomic_fetch_add(v.done + j * NPH + p, one, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// job j and item i of workgroup `rel` in phase p: itoff[p][j] <= rel < itoff[p][j + 1]
+// (every job has at least one item in every phase)
+__device__ __forceinline__ const Geo &locate(const GroupView &v, int p, int rel, int *item) {
+    ConstI32 *off = v.itoff + p * (v.njobs + 1);
+    int lo = 0, hi = v.njobs;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= rel) lo = mid; else hi = mid;
     }
+    *item = rel - off[lo];
+    return *(const Geo *)(v.jobs + lo);
 }
 
 }  // namespace hk

@@ -12,10 +12,6 @@ __global__ __launch_bounds__(WG) void k_local(Geo g) {
     phase_local(g, blockIdx.x, s);
 }
 
-// the node phases (global union-find, node labels) are latency bound and
-// carry little work per brick: small workgroups keep many bricks in flight
-constexpr int WG_NODES = 256;
-
 __global__ __launch_bounds__(WG_NODES) void k_merge(Geo g) { phase_merge(g, blockIdx.x); }
 
 __global__ __launch_bounds__(WG_NODES) void k_roots(Geo g) {

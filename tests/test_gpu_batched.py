@@ -1,4 +1,4 @@
-"""GPU parity of the batched persistent launch: every job of a mix equals the
+"""GPU parity of the batched launches: every job of a mix equals the
 same job labelled alone and the oracle, bit for bit; hipGraph replays of a
 captured batched call equal the eager call."""
 from __future__ import annotations
@@ -83,7 +83,7 @@ def test_config5_stream(hk):
 
 def test_graph_capture_replay(hk):
     """Capture one batched call in a hipGraph and replay it; every replay must
-    equal the eager result (counters are reset by the captured table copy)."""
+    equal the eager result."""
     items = _mix(16, seed=21)
     jobs = []
     for phi_np, m in items:
