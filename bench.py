@@ -10,7 +10,11 @@ Prints ONE JSON line with the throughput in Gsites/s, the roofline of the
 dominant kernel (algorithmic bytes over its live-measured average duration,
 HIP events on the launch stream), the oracle timed on a bounded slab of the
 same workload on the host cores, and the batched-vs-per-lattice comparison
-on the 256-lattice stream.
+on the 256-lattice stream, plus the same stream through the continuous-
+batching server (closed loop and Poisson arrivals with p50/p99 latency).
+
+``--summarize-pmc`` turns two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE)
+of ``bench.py --calib-copy`` into the traffic figure of the roofline.
 """
 from __future__ import annotations
 
@@ -141,7 +145,117 @@ def bench_batched(hk, torch, warmup, reps):
     out["jobs"] = len(bufs)
     out["sites"] = total
     assert hk.device_error() == 0
+    return out, bufs
+
+
+def bench_served(hk, torch, bufs, capacity_jobs_s, runs=4, slots=3, max_batch=64):
+    """The config-5 lattices through the continuous-batching server.
+
+    closed loop: every request present at t0 (server capacity);
+    poisson: the arrival trace of rate 0.7 x the batched capacity (seeds 5..),
+    replayed by submitting it ahead of time, latency = completion observed by
+    the server - scheduled arrival."""
+    import numpy as np
+
+    from paper_1405_1931_amd import workloads as W
+    from paper_1405_1931_amd.serve import Server
+
+    jobs = [(b[0], b[1]) for b in bufs]
+    sites = sum(phi.numel() for phi, _ in jobs)
+    with Server(1 << 20, simulate=(0, 0.0)) as probe:
+        arena = int(1.25 * sum(probe.footprint(phi.shape) for phi, _ in jobs)) + (64 << 20)
+    out = {"slots": slots, "max_batch": max_batch, "arena_bytes": arena, "jobs": len(jobs)}
+    with Server(arena, slots=slots, max_batch=max_batch) as s:
+        def run(arrivals_s, t_lead_ns=2_000_000):
+            t0 = s.now_ns() + t_lead_ns
+            ts = [s.submit(phi, m, arrival_ns=t0 + int(a * 1e9)) for (phi, m), a in zip(jobs, arrivals_s)]
+            s.drain(120)
+            lats = [s.latency_ns(t) for t in ts]
+            ends = [t0 + int(a * 1e9) + l for a, l in zip(arrivals_s, lats)]
+            makespan = max(ends) - t0
+            for t in ts:
+                s.release(t)
+            return lats, makespan
+
+        zeros = [0.0] * len(jobs)
+        run(zeros)  # warm-up
+        s.reset_stats()
+        lats, mk = run(zeros)
+        st = s.stats()
+        out["closed_loop"] = {"ms": round(mk / 1e6, 4), "gsites_per_s": round(sites / mk, 3),
+                              "jobs_per_s": round(len(jobs) / mk * 1e9, 1), "batches": st["batches"],
+                              "p50_ms": round(float(np.percentile(lats, 50)) / 1e6, 4),
+                              "p99_ms": round(float(np.percentile(lats, 99)) / 1e6, 4)}
+        lam = 0.7 * capacity_jobs_s
+        pooled, per_run = [], []
+        s.reset_stats()
+        for r in range(runs):
+            arr = W.poisson_arrivals(len(jobs), lam, seed=5 + r)
+            lats, mk = run(list(arr))
+            pooled += lats
+            per_run.append({"seed": 5 + r, "ms": round(mk / 1e6, 4), "gsites_per_s": round(sites / mk, 3),
+                            "jobs_per_s": round(len(jobs) / mk * 1e9, 1)})
+        st = s.stats()
+        pooled = np.array(pooled, dtype=np.float64)
+        out["poisson"] = {"rate_jobs_per_s": round(lam, 1), "runs": per_run, "samples": int(pooled.size),
+                          "p50_ms": round(float(np.percentile(pooled, 50, method="inverted_cdf")) / 1e6, 4),
+                          "p99_ms": round(float(np.percentile(pooled, 99, method="inverted_cdf")) / 1e6, 4),
+                          "max_ms": round(float(pooled.max()) / 1e6, 4),
+                          "jobs_per_s": round(float(np.mean([r["jobs_per_s"] for r in per_run])), 1),
+                          "gsites_per_s": round(float(np.mean([r["gsites_per_s"] for r in per_run])), 3),
+                          "batches": st["batches"], "mean_batch_jobs": round(st["mean_batch_jobs"], 2),
+                          "arena_peak_bytes": st["arena_peak"]}
     return out
+
+
+def calibration_copy(torch, nbytes=1 << 30):
+    """One plain device copy of `nbytes` (read nbytes + write nbytes), for
+    scaling the HBM byte counters of a counter run."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def summarize_pmc(fetch_dir, write_dir, kernel, tag, calib_bytes=1 << 30):
+    """Per-launch HBM bytes of `kernel` from two rocprofv3 --pmc runs (CSV
+    output; FETCH_SIZE then WRITE_SIZE, KiB per dispatch), each scaled by the
+    same counter on the calibration copy of calib_bytes; written to
+    profiles/traffic_<kernel>_<tag>.json with the kernel source hash."""
+    import csv
+    import glob
+
+    def per_kernel(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                rows += [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
+        vals = {}
+        for r in rows:
+            vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        return vals
+
+    out = {"kernel": kernel, "workload": tag, "source_sha": kernel_source_hash(), "calibration_bytes": calib_bytes}
+    total = 0.0
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        vals = per_kernel(d, counter)
+        mine = [v for name, vs in vals.items() if name.split("(")[0].endswith(kernel) for v in vs]
+        copy = [v for name, vs in vals.items() if "copy" in name.lower() or "elementwise" in name.lower() for v in vs]
+        if not mine or not copy:
+            raise SystemExit(f"{counter}: kernel {kernel} or calibration copy not found in {d}")
+        raw = sum(mine) / len(mine)
+        cal = max(copy)  # the 1 GiB copy is the largest copy of the run
+        factor = calib_bytes / cal
+        out[counter] = {"raw_bytes_per_launch": raw, "calibration_raw_bytes": cal, "factor": factor,
+                        "bytes_per_launch": raw * factor, "launches": len(mine)}
+        total += raw * factor
+    out["bytes_per_launch"] = total
+    path = os.path.join(PROFILES, f"traffic_{kernel}_{tag}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
 
 
 def main():
@@ -154,7 +268,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
+    ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true", help="run one 1 GiB device copy (counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "TAG"),
+                    help="write profiles/traffic_<KERNEL>_<TAG>.json from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -169,6 +290,8 @@ def main():
     from paper_1405_1931_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calib_copy:
+        calibration_copy(torch)
     edge = args.edge
     mask = 7
     t0 = time.time()
@@ -209,14 +332,17 @@ def main():
         tot, calls = hk.profile_read()
         hk.profile_enable(False)
         kernels = {name: round(v / calls, 4) for name, v in tot.items()}
-        dom = max(kernels, key=kernels.get)
+        # the longest kernel that moves algorithmic bytes (the others move
+        # only intermediate data, whose bytes count as overhead)
+        dom = max((kk for kk in kernels if algorithmic_bytes(kk, n, k)), key=kernels.get)
         alg = algorithmic_bytes(dom, n, k)
         dur_s = kernels[dom] / 1e3
         achieved = alg / dur_s / 1e9 if alg else 0.0
         roofline = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": load_traffic(dom, f"percolation{edge}"),
-                    "avg_ms": kernels[dom], "algorithmic_bytes": alg}
+                    "avg_ms": kernels[dom], "algorithmic_bytes": alg,
+                    "longest_kernel": max(kernels, key=kernels.get)}
         log(f"kernels (ms/launch): {kernels}")
 
     path_bytes = 8 * n + 8 * k + 8
@@ -244,8 +370,17 @@ def main():
     del labels, sizes
     if not args.no_batched:
         torch.cuda.empty_cache()
-        result["batched"] = bench_batched(hk, torch, warmup=2, reps=5)
+        result["batched"], bufs = bench_batched(hk, torch, warmup=2, reps=5)
         log(f"batched: {result['batched']}")
+        if not args.no_served:
+            cap = result["batched"]["batched"]["jobs_per_s"]
+            served = bench_served(hk, torch, bufs, cap)
+            pl = result["batched"]["per_lattice"]["jobs_per_s"]
+            served["closed_loop"]["speedup_vs_per_lattice"] = round(served["closed_loop"]["jobs_per_s"] / pl, 2)
+            served["poisson"]["speedup_vs_per_lattice"] = round(served["poisson"]["jobs_per_s"] / pl, 2)
+            result["served"] = served
+            log(f"served: {served}")
+        del bufs
     if not args.no_cpu_baseline:
         planes = min(args.cpu_planes, edge)
         result["cpu_baseline"] = cpu_baseline(phi_np, mask, planes)

@@ -54,7 +54,8 @@ typedef enum {
     HK_ERR_TOO_LARGE = -2,    /* nx*ny*nz > INT32_MAX, or no brick shape fits */
     HK_ERR_NO_WORKSPACE = -3, /* workspace too small while the stream is being captured */
     HK_ERR_HIP = -4,          /* a HIP runtime call or a launch failed */
-    HK_ERR_DEVICE = -5        /* hk_device_error: a device-side check fired */
+    HK_ERR_DEVICE = -5,       /* hk_device_error: a device-side check fired */
+    HK_ERR_TIMEOUT = -6       /* hk_server_wait / hk_server_drain: time limit reached */
 } hk_status;
 
 /*
@@ -156,6 +157,90 @@ const char *hk_phase_name(int32_t i);
  * or HK_ERR_DEVICE when a flag was set (code written to *code if non-NULL).
  */
 int hk_device_error(hipStream_t stream, int32_t *code);
+
+/*
+ * ------------------------------------------------------------------------
+ * Labelling server (continuous batching on one device).
+ *
+ * A server owns one device arena of `arena_bytes`, allocated at creation;
+ * nothing is allocated per request.  Each request (a device-resident phi,
+ * Sec. 2 condition, Sec. 3 periodicity as in hk_label) takes
+ * hk_server_footprint() arena bytes: its outputs, labels [N] int32 and sizes
+ * [ceil(N/2)] int64 (the Sec. 3 bound), which stay in the arena until
+ * hk_server_release, plus its share of the workspace of the batch it runs
+ * in, freed when that batch completes.  Requests are admitted first come
+ * first served when arena space and one of `n_slots` batch slots are free;
+ * a free slot takes the longest prefix of the waiting queue that fits (at
+ * most max_batch_jobs requests) and labels it with the batched kernels on
+ * its own stream, so up to n_slots batches run concurrently and requests
+ * that arrive while others run join the next batch.  A scheduler thread,
+ * started by hk_server_create and joined by hk_server_destroy, does the
+ * admission and polls completion.
+ *
+ * Ownership: phi is the caller's and must stay valid and unchanged until
+ * the request is done (hk_server_poll returns 1) or failed.  Output
+ * pointers from hk_server_result point into the arena and are valid until
+ * hk_server_release of that ticket.  Results are identical to hk_label of
+ * the same lattice alone.
+ *
+ * Latency of a request = time the scheduler observed its batch complete -
+ * arrival, where arrival is the `arrival_ns` given to hk_server_submit on
+ * the hk_server_now_ns() clock (0 = the submission time).  A request is not
+ * admitted before its arrival time, so an arrival trace can be replayed by
+ * submitting it ahead of time (in arrival order: admission is in submission
+ * order).
+ *
+ * Errors: invalid arguments return HK_ERR_INVALID_ARG, a request larger
+ * than the whole arena HK_ERR_TOO_LARGE (at submission).  A failed batch
+ * marks each of its requests failed with the status (HK_ERR_HIP, or
+ * HK_ERR_DEVICE when a device-side check fired); poll/wait/result return it.
+ * All calls are thread-safe.
+ * ------------------------------------------------------------------------
+ */
+typedef struct hk_server hk_server;
+
+typedef struct {
+    int64_t submitted, completed, failed;  /* since creation or the last reset */
+    int64_t batches;
+    double mean_batch_jobs;
+    int64_t pending, running;              /* now */
+    int64_t sites_completed;
+    int64_t arena_bytes, arena_in_use, arena_peak;
+    int64_t latency_samples;               /* completed requests */
+    int64_t latency_p50_ns, latency_p99_ns, latency_max_ns;  /* nearest rank */
+    double latency_mean_ns;
+    int64_t span_ns;                       /* first batch launch to last completion */
+} hk_server_stats;
+
+/* n_slots in [1, 16] batches in flight; max_batch_jobs in [1, 65536]. */
+int hk_server_create(int64_t arena_bytes, int32_t n_slots, int32_t max_batch_jobs, hk_server **out);
+/* The same scheduler with a simulated device (no HIP call is made): a batch
+ * completes batch_fixed_ns + ns_per_site * (its sites) after its launch and
+ * every K is 0; output pointers are arena offsets.  phi may be NULL.  For
+ * exercising admission and batching without a GPU. */
+int hk_server_create_simulated(int64_t arena_bytes, int32_t n_slots, int32_t max_batch_jobs, int64_t batch_fixed_ns,
+                               double ns_per_site, hk_server **out);
+/* Arena bytes one request of this shape needs when it runs alone. */
+int64_t hk_server_footprint(int32_t nx, int32_t ny, int32_t nz);
+/* The server clock (steady, nanoseconds). */
+int64_t hk_server_now_ns(void);
+int hk_server_submit(hk_server *s, const float *phi, int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask,
+                     int64_t arrival_ns, uint64_t *ticket);
+/* 1 done, 0 waiting or running, < 0 failed (its status) or unknown ticket. */
+int hk_server_poll(hk_server *s, uint64_t ticket);
+/* Block until the request is done (HK_OK), failed (its status) or timeout_ns passed (HK_ERR_TIMEOUT). */
+int hk_server_wait(hk_server *s, uint64_t ticket, int64_t timeout_ns);
+/* Block until no request waits or runs. */
+int hk_server_drain(hk_server *s, int64_t timeout_ns);
+/* Device pointers of a done request's outputs, its K and latency (any out pointer may be NULL). */
+int hk_server_result(hk_server *s, uint64_t ticket, int32_t **labels, int64_t *n_clusters, int64_t **sizes,
+                     int64_t *latency_ns);
+/* Free a done or failed request's outputs, or withdraw a waiting one; a running one is refused. */
+int hk_server_release(hk_server *s, uint64_t ticket);
+int hk_server_read_stats(hk_server *s, hk_server_stats *out);
+int hk_server_reset_stats(hk_server *s);
+/* Stop the scheduler, wait for running batches, free the arena; waiting requests are dropped. */
+int hk_server_destroy(hk_server *s);
 
 #ifdef __cplusplus
 }

@@ -19,6 +19,7 @@ HK_ERR_TOO_LARGE = -2
 HK_ERR_NO_WORKSPACE = -3
 HK_ERR_HIP = -4
 HK_ERR_DEVICE = -5
+HK_ERR_TIMEOUT = -6
 
 
 class HkJob(ctypes.Structure):
@@ -33,6 +34,32 @@ class HkJob(ctypes.Structure):
         ("sizes", ctypes.c_void_p),
     ]
 
+
+class HkServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64),
+        ("completed", ctypes.c_int64),
+        ("failed", ctypes.c_int64),
+        ("batches", ctypes.c_int64),
+        ("mean_batch_jobs", ctypes.c_double),
+        ("pending", ctypes.c_int64),
+        ("running", ctypes.c_int64),
+        ("sites_completed", ctypes.c_int64),
+        ("arena_bytes", ctypes.c_int64),
+        ("arena_in_use", ctypes.c_int64),
+        ("arena_peak", ctypes.c_int64),
+        ("latency_samples", ctypes.c_int64),
+        ("latency_p50_ns", ctypes.c_int64),
+        ("latency_p99_ns", ctypes.c_int64),
+        ("latency_max_ns", ctypes.c_int64),
+        ("latency_mean_ns", ctypes.c_double),
+        ("span_ns", ctypes.c_int64),
+    ]
+
+
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
 
 _SIGS = {
     "hk_label": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
@@ -54,6 +81,21 @@ _SIGS = {
                                        ctypes.POINTER(ctypes.c_int32)]),
     "hk_phase_count": (ctypes.c_int32, []),
     "hk_phase_name": (ctypes.c_char_p, [ctypes.c_int32]),
+    "hk_server_create": (ctypes.c_int, [_I64, _I32, _I32, ctypes.POINTER(_P)]),
+    "hk_server_create_simulated": (ctypes.c_int, [_I64, _I32, _I32, _I64, ctypes.c_double, ctypes.POINTER(_P)]),
+    "hk_server_footprint": (_I64, [_I32, _I32, _I32]),
+    "hk_server_now_ns": (_I64, []),
+    "hk_server_submit": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, ctypes.c_uint32, _I64,
+                                        ctypes.POINTER(ctypes.c_uint64)]),
+    "hk_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64]),
+    "hk_server_wait": (ctypes.c_int, [_P, ctypes.c_uint64, _I64]),
+    "hk_server_drain": (ctypes.c_int, [_P, _I64]),
+    "hk_server_result": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(_P), ctypes.POINTER(_I64),
+                                        ctypes.POINTER(_P), ctypes.POINTER(_I64)]),
+    "hk_server_release": (ctypes.c_int, [_P, ctypes.c_uint64]),
+    "hk_server_read_stats": (ctypes.c_int, [_P, ctypes.POINTER(HkServerStats)]),
+    "hk_server_reset_stats": (ctypes.c_int, [_P]),
+    "hk_server_destroy": (ctypes.c_int, [_P]),
 }
 
 _lib = None

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhk.so")
-SOURCES = ["hk_kernels.hip", "hk_api.hip", "hk_batched.hip"]
+SOURCES = ["hk_kernels.hip", "hk_api.hip", "hk_batched.hip", "hk_server.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -17,6 +17,7 @@ HIPCC_FLAGS = [
     "-fPIC",
     "-shared",
     "-Wall",
+    "-pthread",
     # keep the compiler from forming packed fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

@@ -355,6 +355,7 @@ const char *hk_status_string(int status) {
         case HK_ERR_NO_WORKSPACE: return "HK_ERR_NO_WORKSPACE: workspace must be reserved before capture";
         case HK_ERR_HIP: return "HK_ERR_HIP: HIP runtime or launch failure";
         case HK_ERR_DEVICE: return "HK_ERR_DEVICE: a device-side check fired";
+        case HK_ERR_TIMEOUT: return "HK_ERR_TIMEOUT: time limit reached";
         default: return "unknown hk status";
     }
 }

@@ -226,6 +226,66 @@ void release_batched() {
     g_arena = CaptureArena();
 }
 
+// Enqueue the table upload and the nine grouped kernels of a validated
+// batch; `ws` holds at least the bytes validate_and_plan reported.  The
+// caller holds the workspace mutex (it guards the staging ring).
+int enqueue_batched(const hk_job *jobs, int n_jobs, const std::vector<Geo> &geos, char *ws, int32_t *err,
+                    hipStream_t stream) {
+    const TableLayout tl = table_layout(n_jobs);
+    std::vector<char> img((size_t)tl.total, 0);
+    int32_t *itoff = (int32_t *)(img.data() + tl.itoff);
+    int64_t items[NPH];
+    for (int p = 0; p < NPH; ++p) {
+        int32_t *off = itoff + p * (n_jobs + 1);
+        int64_t acc = 0;
+        for (int j = 0; j < n_jobs; ++j) {
+            off[j] = (int32_t)acc;
+            acc += items_of(geos[j], p);
+            if (acc > INT32_MAX) return HK_ERR_TOO_LARGE;
+        }
+        off[n_jobs] = (int32_t)acc;
+        items[p] = acc;
+    }
+    char *table = ws;
+    char *cursor = ws + tl.total;
+    Geo *hj = (Geo *)(img.data() + tl.jobs);
+    for (int j = 0; j < n_jobs; ++j) {
+        Geo g = geos[j];
+        bind_lattice(&g, cursor);
+        cursor += al(lattice_bytes(g));
+        g.err = err;
+        g.phi = jobs[j].phi;
+        g.labels = jobs[j].labels;
+        g.n_clusters = jobs[j].n_clusters;
+        g.sizes = jobs[j].sizes;
+        hj[j] = g;
+    }
+    const int rc = upload_table(img, table, stream);
+    if (rc != HK_OK) return rc;
+
+    GroupView v;
+    v.jobs = (ConstGeo *)(table + tl.jobs);
+    v.itoff = (ConstI32 *)(table + tl.itoff);
+    v.njobs = n_jobs;
+    const dim3 blk(WG), small(WG_NODES);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(kb_pack, dim3((unsigned)items[0]), blk, 0, stream, v);
+    hipLaunchKernelGGL(kb_local, dim3((unsigned)items[1]), blk, 0, stream, v);
+    hipLaunchKernelGGL(kb_merge, dim3((unsigned)items[2]), small, 0, stream, v);
+    hipLaunchKernelGGL(kb_roots, dim3((unsigned)items[3]), small, 0, stream, v);
+    hipLaunchKernelGGL(kb_rowsum, dim3((unsigned)items[4]), blk, 0, stream, v);
+    hipLaunchKernelGGL(kb_scanblk, dim3((unsigned)items[5]), blk, 0, stream, v);
+    hipLaunchKernelGGL(kb_rowpre, dim3((unsigned)items[6]), blk, 0, stream, v);
+    hipLaunchKernelGGL(kb_canon, dim3((unsigned)items[7]), small, 0, stream, v);
+    hipLaunchKernelGGL(kb_write, dim3((unsigned)items[8]), blk, 0, stream, v);
+    return hipGetLastError() == hipSuccess ? HK_OK : HK_ERR_HIP;
+}
+
+// validation and workspace size of a batch, exposed to the server
+int plan_batched(const hk_job *jobs, int n_jobs, std::vector<Geo> *geos, int64_t *bytes) {
+    return validate_and_plan(jobs, n_jobs, true, geos, bytes);
+}
+
 }  // namespace hk
 
 using namespace hk;
@@ -248,63 +308,12 @@ int hk_label_batched(const hk_job *jobs, int32_t n_jobs, hipStream_t stream) {
     int64_t bytes = 0;
     int rc = validate_and_plan(jobs, n_jobs, true, &geos, &bytes);
     if (rc != HK_OK) return rc;
-
-    // item offsets of every job within every phase
-    const TableLayout tl = table_layout(n_jobs);
-    std::vector<char> img((size_t)tl.total, 0);
-    int32_t *itoff = (int32_t *)(img.data() + tl.itoff);
-    int64_t items[NPH];
-    for (int p = 0; p < NPH; ++p) {
-        int32_t *off = itoff + p * (n_jobs + 1);
-        int64_t acc = 0;
-        for (int j = 0; j < n_jobs; ++j) {
-            off[j] = (int32_t)acc;
-            acc += items_of(geos[j], p);
-            if (acc > INT32_MAX) return HK_ERR_TOO_LARGE;
-        }
-        off[n_jobs] = (int32_t)acc;
-        items[p] = acc;
-    }
-
     std::lock_guard<std::mutex> lk(workspace_mutex());
     char *base = nullptr;
     int32_t *err = nullptr;
     rc = acquire_workspace(stream, bytes, &base, &err);
     if (rc != HK_OK) return rc;
-    char *table = base;
-    char *cursor = base + tl.total;
-    Geo *hj = (Geo *)(img.data() + tl.jobs);
-    for (int j = 0; j < n_jobs; ++j) {
-        Geo g = geos[j];
-        bind_lattice(&g, cursor);
-        cursor += al(lattice_bytes(g));
-        g.err = err;
-        g.phi = jobs[j].phi;
-        g.labels = jobs[j].labels;
-        g.n_clusters = jobs[j].n_clusters;
-        g.sizes = jobs[j].sizes;
-        hj[j] = g;
-    }
-    rc = upload_table(img, table, stream);
-    if (rc != HK_OK) return rc;
-
-    GroupView v;
-    v.jobs = (ConstGeo *)(table + tl.jobs);
-    v.itoff = (ConstI32 *)(table + tl.itoff);
-    v.njobs = n_jobs;
-    const dim3 blk(WG), small(WG_NODES);
-    (void)hipGetLastError();
-    hipLaunchKernelGGL(kb_pack, dim3((unsigned)items[0]), blk, 0, stream, v);
-    hipLaunchKernelGGL(kb_local, dim3((unsigned)items[1]), blk, 0, stream, v);
-    hipLaunchKernelGGL(kb_merge, dim3((unsigned)items[2]), small, 0, stream, v);
-    hipLaunchKernelGGL(kb_roots, dim3((unsigned)items[3]), small, 0, stream, v);
-    hipLaunchKernelGGL(kb_rowsum, dim3((unsigned)items[4]), blk, 0, stream, v);
-    hipLaunchKernelGGL(kb_scanblk, dim3((unsigned)items[5]), blk, 0, stream, v);
-    hipLaunchKernelGGL(kb_rowpre, dim3((unsigned)items[6]), blk, 0, stream, v);
-    hipLaunchKernelGGL(kb_canon, dim3((unsigned)items[7]), small, 0, stream, v);
-    hipLaunchKernelGGL(kb_write, dim3((unsigned)items[8]), blk, 0, stream, v);
-    if (hipGetLastError() != hipSuccess) return HK_ERR_HIP;
-    return HK_OK;
+    return enqueue_batched(jobs, n_jobs, geos, base, err, stream);
 }
 
 }  // extern "C"
