@@ -138,6 +138,30 @@ int hk_get_brick(int32_t nx, int32_t ny, int32_t nz, int32_t *by, int32_t *bz);
 int hk_set_brick_for_shape(int32_t nx, int32_t ny, int32_t nz, int32_t by, int32_t bz);
 
 /*
+ * Brick autotuner.  hk_autotune runs hk_label on this lattice once per
+ * candidate brick shape (powers of two, by*bz between min(64, what the
+ * lattice allows) and 256) -- one untimed call, then `reps` timed calls
+ * between HIP events on `stream`, which it synchronises -- and installs the
+ * fastest shape for the lattice's size bucket (as hk_set_brick_for_shape).
+ * It writes the shape to *by, *bz and its mean time in ms to *ms (each may
+ * be NULL).  The outputs end holding the result of one more call with the
+ * chosen shape, identical to hk_label's.  hk_autotune_batched does the same
+ * with hk_label_batched over `jobs`, choosing one shape for the whole batch
+ * and installing it for the bucket of every job.  While a tuning run lasts
+ * it overrides the brick choice of every other call.
+ */
+int hk_autotune(const float *phi, int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask, int32_t *labels,
+                int64_t *n_clusters, int64_t *sizes, int32_t reps, hipStream_t stream, int32_t *by, int32_t *bz,
+                float *ms);
+int hk_autotune_batched(const hk_job *jobs, int32_t n_jobs, int32_t reps, hipStream_t stream, int32_t *by,
+                        int32_t *bz, float *ms);
+/* Write the tuned table to a text file ("log2(nx) log2(ny) log2(nz) by bz"
+ * per line) / install the entries of such a file (a malformed file installs
+ * nothing and returns HK_ERR_INVALID_ARG). */
+int hk_tune_save(const char *path);
+int hk_tune_load(const char *path);
+
+/*
  * Per-kernel timing (a tracing aid, off by default).  While enabled, every
  * hk_label call records a HIP event on its own stream before each of its
  * kernels and after the last one.  hk_profile_read synchronises on those

@@ -167,6 +167,43 @@ def set_brick_for_shape(nx, ny, nz, by, bz):
     _lib.check(_lib.load().hk_set_brick_for_shape(nx, ny, nz, by, bz), "hk_set_brick_for_shape")
 
 
+def autotune(phi, periodic=0, reps: int = 3, stream=None):
+    """Time every candidate brick shape on this lattice and install the
+    fastest for its size bucket; returns (by, bz, ms)."""
+    import torch
+
+    _check_phi(phi)
+    nz, ny, nx = phi.shape
+    labels = torch.empty_like(phi, dtype=torch.int32)
+    k = torch.zeros(1, dtype=torch.int64, device=phi.device)
+    sz = torch.empty(max(1, max_clusters(nx, ny, nz)), dtype=torch.int64, device=phi.device)
+    by, bz, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+    rc = _lib.load().hk_autotune(phi.data_ptr(), nx, ny, nz, mask_of(periodic), labels.data_ptr(), k.data_ptr(),
+                                 sz.data_ptr(), int(reps), _stream_handle(stream), ctypes.byref(by),
+                                 ctypes.byref(bz), ctypes.byref(ms))
+    _lib.check(rc, "hk_autotune")
+    return by.value, bz.value, ms.value
+
+
+def autotune_batched(jobs, reps: int = 3, stream=None):
+    """One brick shape for the whole batch ``jobs`` (as for label_batched_into),
+    installed for every job's size bucket; returns (by, bz, ms)."""
+    arr = _jobs_array(jobs)
+    by, bz, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+    rc = _lib.load().hk_autotune_batched(arr, len(jobs), int(reps), _stream_handle(stream), ctypes.byref(by),
+                                         ctypes.byref(bz), ctypes.byref(ms))
+    _lib.check(rc, "hk_autotune_batched")
+    return by.value, bz.value, ms.value
+
+
+def tune_save(path: str):
+    _lib.check(_lib.load().hk_tune_save(str(path).encode()), "hk_tune_save")
+
+
+def tune_load(path: str):
+    _lib.check(_lib.load().hk_tune_load(str(path).encode()), "hk_tune_load")
+
+
 def profile_enable(on: bool = True):
     _lib.check(_lib.load().hk_profile_enable(1 if on else 0), "hk_profile_enable")
 

@@ -81,6 +81,12 @@ _SIGS = {
                                        ctypes.POINTER(ctypes.c_int32)]),
     "hk_phase_count": (ctypes.c_int32, []),
     "hk_phase_name": (ctypes.c_char_p, [ctypes.c_int32]),
+    "hk_autotune": (ctypes.c_int, [_P, _I32, _I32, _I32, ctypes.c_uint32, _P, _P, _P, _I32, _P,
+                                   ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)]),
+    "hk_autotune_batched": (ctypes.c_int, [ctypes.POINTER(HkJob), _I32, _I32, _P, ctypes.POINTER(_I32),
+                                           ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)]),
+    "hk_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "hk_tune_load": (ctypes.c_int, [ctypes.c_char_p]),
     "hk_server_create": (ctypes.c_int, [_I64, _I32, _I32, ctypes.POINTER(_P)]),
     "hk_server_create_simulated": (ctypes.c_int, [_I64, _I32, _I32, _I64, ctypes.c_double, ctypes.POINTER(_P)]),
     "hk_server_footprint": (_I64, [_I32, _I32, _I32]),

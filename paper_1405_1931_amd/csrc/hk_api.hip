@@ -233,6 +233,28 @@ int get_workspace(hipStream_t stream, int64_t bytes, Workspace **out) {
 
 }  // namespace
 
+// accessors for the autotuner (hk_tune.hip); all take g_brick_mu
+void brick_forced(int *by, int *bz) {
+    std::lock_guard<std::mutex> lk(g_brick_mu);
+    *by = g_force_by;
+    *bz = g_force_bz;
+}
+void brick_force(int by, int bz) {
+    std::lock_guard<std::mutex> lk(g_brick_mu);
+    g_force_by = by;
+    g_force_bz = bz;
+}
+std::vector<std::pair<uint32_t, std::pair<int, int>>> brick_table() {
+    std::lock_guard<std::mutex> lk(g_brick_mu);
+    return {g_tuned.begin(), g_tuned.end()};
+}
+void brick_table_set(uint32_t bucket, int by, int bz) {
+    std::lock_guard<std::mutex> lk(g_brick_mu);
+    g_tuned[bucket] = {by, bz};
+}
+uint32_t brick_bucket(int nx, int ny, int nz) { return bucket_of(nx, ny, nz); }
+
+
 // exposed to the batched path
 int plan_lattice_ext(int32_t nx, int32_t ny, int32_t nz, uint32_t mask, Geo *g) {
     return plan_lattice(nx, ny, nz, mask, g, true);

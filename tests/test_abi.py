@@ -45,7 +45,7 @@ def test_max_clusters(lib):
 
 
 def test_status_strings(lib):
-    for s in (0, -1, -2, -3, -4, -5):
+    for s in (0, -1, -2, -3, -4, -5, -6):
         assert lib.hk_status_string(s).startswith(b"HK_")
     assert b"unknown" in lib.hk_status_string(42)
 
@@ -98,3 +98,37 @@ def test_sizing_and_bricks(lib):
     # thin lattices still get a plan
     assert lib.hk_workspace_bytes(1, 1, 1 << 30) > 0
     assert lib.hk_workspace_bytes(1 << 30, 1, 1) > 0
+
+
+def test_tune_table_save_and_load(lib, tmp_path):
+    by, bz = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.hk_set_brick_for_shape(300, 90, 70, 8, 16) == 0
+    path = str(tmp_path / "bricks.txt").encode()
+    assert lib.hk_tune_save(path) == 0
+    lines = [l for l in open(path).read().splitlines() if not l.startswith("#")]
+    assert "9 7 7 8 16" in lines  # ceil(log2) of 300, 90, 70
+    assert lib.hk_set_brick_for_shape(300, 90, 70, 0, 0) == 0
+    assert lib.hk_tune_load(path) == 0
+    assert lib.hk_get_brick(260, 100, 127, ctypes.byref(by), ctypes.byref(bz)) == 0
+    assert (by.value, bz.value) == (8, 16)
+    assert lib.hk_set_brick_for_shape(300, 90, 70, 0, 0) == 0
+    # malformed files install nothing
+    bad = tmp_path / "bad.txt"
+    bad.write_text("9 7 7 8 16\n9 7 7 3 16\n")
+    assert lib.hk_tune_load(str(bad).encode()) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_get_brick(300, 90, 70, ctypes.byref(by), ctypes.byref(bz)) == 0
+    assert (by.value, bz.value) != (8, 16)
+    assert lib.hk_tune_load(str(tmp_path / "missing.txt").encode()) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_tune_load(None) == _lib.HK_ERR_INVALID_ARG
+
+
+def test_autotune_argument_errors_without_gpu(lib):
+    dummy = ctypes.c_void_p(0x1000)
+    by, bz, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+    args = (ctypes.byref(by), ctypes.byref(bz), ctypes.byref(ms))
+    assert lib.hk_autotune(None, 4, 4, 4, 0, dummy, dummy, None, 3, None, *args) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_autotune(dummy, 0, 4, 4, 0, dummy, dummy, None, 3, None, *args) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_autotune(dummy, 4, 4, 4, 9, dummy, dummy, None, 3, None, *args) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_autotune(dummy, 4, 4, 4, 0, dummy, dummy, None, 0, None, *args) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_autotune_batched(None, 2, 3, None, *args) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_autotune_batched(None, 0, 3, None, *args) == _lib.HK_ERR_INVALID_ARG

@@ -112,3 +112,44 @@ def test_graph_capture_replay(hk):
             assert torch.equal(j[2], el), rep
             assert torch.equal(j[4][:ek], es), rep
     assert hk.device_error(stream=s) == 0
+
+
+def test_autotune_installs_a_shape_and_keeps_results_exact(hk, tmp_path):
+    """The tuner times every candidate brick shape, installs the fastest for
+    the lattice's bucket, and the labelling stays bit-exact under it."""
+    phi_np = W.percolation((70, 90, 130), 0.3116, seed=41)
+    phi = torch.from_numpy(phi_np).cuda()
+    print("[autotune] single lattice 130x90x70", flush=True)
+    by, bz, ms = hk.autotune(phi, 7, reps=2)
+    assert by * bz <= 256 and ms > 0
+    assert hk.get_brick(130, 90, 70) == (by, bz)
+    lab, k, sz = hk.label(phi, 7)
+    exp = oracle.label(phi_np, 7)
+    assert k == exp[1] and np.array_equal(lab.cpu().numpy(), exp[0]) and np.array_equal(sz.cpu().numpy(), exp[2])
+    path = tmp_path / "bricks.txt"
+    hk.tune_save(path)
+    hk.set_brick_for_shape(130, 90, 70, 0, 0)
+    hk.tune_load(path)
+    assert hk.get_brick(130, 90, 70) == (by, bz)
+    hk.set_brick_for_shape(130, 90, 70, 0, 0)
+
+    items = _mix(12, seed=77, lo=8, hi=100)
+    jobs = []
+    for phi_np, m in items:
+        p = torch.from_numpy(phi_np).cuda()
+        nz, ny, nx = p.shape
+        jobs.append((p, m, torch.empty_like(p, dtype=torch.int32), torch.zeros(1, dtype=torch.int64, device="cuda"),
+                     torch.empty(max(1, hk.max_clusters(nx, ny, nz)), dtype=torch.int64, device="cuda")))
+    print("[autotune] batch of 12", flush=True)
+    by, bz, ms = hk.autotune_batched(jobs, reps=2)
+    assert by * bz <= 256 and ms > 0
+    torch.cuda.synchronize()
+    for j, ((phi_np, m), job) in enumerate(zip(items, jobs)):
+        exp = oracle.label(phi_np, m)
+        k = int(job[3].item())
+        assert k == exp[1] and np.array_equal(job[2].cpu().numpy(), exp[0]), f"job {j}"
+        assert np.array_equal(job[4][:k].cpu().numpy(), exp[2]), f"job {j}"
+    for phi_np, _ in items:
+        nz, ny, nx = phi_np.shape
+        hk.set_brick_for_shape(nx, ny, nz, 0, 0)
+    assert hk.device_error() == 0
