@@ -49,10 +49,11 @@ def kernel_source_hash():
 
 def algorithmic_bytes(kernel, n, k):
     """Bytes a kernel must move by the method's definition: phi is read once
-    (4 B/site), labels written once (4 B/site), sizes written once
-    (8 B/cluster) plus K (8 B).  Every other byte is implementation
-    overhead, so the other kernels have no algorithmic share."""
-    if kernel == "k_pack":
+    (4 B/site, by the brick kernel), labels written once (4 B/site), sizes
+    written once (8 B/cluster) plus K (8 B).  Every other byte is
+    implementation overhead, so the other kernels have no algorithmic
+    share."""
+    if kernel == "k_local":
         return 4 * n
     if kernel == "k_write":
         return 4 * n + 8 * k

@@ -28,63 +28,57 @@
 
 namespace hk {
 
-__global__ __launch_bounds__(WG) void kb_pack(GroupView v) {
-    int i;
-    const Geo &g = locate(v, 0, blockIdx.x, &i);
-    phase_pack(g, i);
-}
-
 __global__ __launch_bounds__(WG) void kb_local(GroupView v) {
     __shared__ LdsBrick s;
     int i;
-    const Geo &g = locate(v, 1, blockIdx.x, &i);
+    const Geo &g = locate(v, 0, blockIdx.x, &i);
     phase_local(g, i, s);
 }
 
 __global__ __launch_bounds__(WG_NODES) void kb_merge(GroupView v) {
     int i;
-    const Geo &g = locate(v, 2, blockIdx.x, &i);
+    const Geo &g = locate(v, 1, blockIdx.x, &i);
     phase_merge(g, i);
 }
 
 __global__ __launch_bounds__(WG_NODES) void kb_roots(GroupView v) {
     __shared__ int32_t hash[2 * HT];
     int i;
-    const Geo &g = locate(v, 3, blockIdx.x, &i);
+    const Geo &g = locate(v, 2, blockIdx.x, &i);
     phase_roots(g, i, hash);
 }
 
 __global__ __launch_bounds__(WG) void kb_rowsum(GroupView v) {
     __shared__ int32_t tmp[32];
     int i;
-    const Geo &g = locate(v, 4, blockIdx.x, &i);
+    const Geo &g = locate(v, 3, blockIdx.x, &i);
     phase_rowsum(g, i, tmp);
 }
 
 __global__ __launch_bounds__(WG) void kb_scanblk(GroupView v) {
     __shared__ int32_t tmp[32];
     int i;
-    const Geo &g = locate(v, 5, blockIdx.x, &i);
+    const Geo &g = locate(v, 4, blockIdx.x, &i);
     phase_scanblk(g, tmp);
 }
 
 __global__ __launch_bounds__(WG) void kb_rowpre(GroupView v) {
     __shared__ int32_t tmp[32];
     int i;
-    const Geo &g = locate(v, 6, blockIdx.x, &i);
+    const Geo &g = locate(v, 5, blockIdx.x, &i);
     phase_rowpre(g, i, tmp);
 }
 
 __global__ __launch_bounds__(WG_NODES) void kb_canon(GroupView v) {
     int i;
-    const Geo &g = locate(v, 7, blockIdx.x, &i);
+    const Geo &g = locate(v, 6, blockIdx.x, &i);
     phase_canon(g, i);
 }
 
 __global__ __launch_bounds__(WG) void kb_write(GroupView v) {
     __shared__ LdsBrick s;
     int i;
-    const Geo &g = locate(v, 8, blockIdx.x, &i);
+    const Geo &g = locate(v, 7, blockIdx.x, &i);
     phase_write(g, i, s);
 }
 
@@ -119,9 +113,9 @@ TableLayout table_layout(int n) {
 
 int items_of(const Geo &g, int p) {
     switch (p) {
-        case 4:
-        case 6: return g.nblk;
-        case 5: return 1;
+        case 3:
+        case 5: return g.nblk;
+        case 4: return 1;
         default: return g.nb;
     }
 }
@@ -226,7 +220,7 @@ void release_batched() {
     g_arena = CaptureArena();
 }
 
-// Enqueue the table upload and the nine grouped kernels of a validated
+// Enqueue the table upload and the eight grouped kernels of a validated
 // batch; `ws` holds at least the bytes validate_and_plan reported.  The
 // caller holds the workspace mutex (it guards the staging ring).
 int enqueue_batched(const hk_job *jobs, int n_jobs, const std::vector<Geo> &geos, char *ws, int32_t *err,
@@ -269,15 +263,14 @@ int enqueue_batched(const hk_job *jobs, int n_jobs, const std::vector<Geo> &geos
     v.njobs = n_jobs;
     const dim3 blk(WG), small(WG_NODES);
     (void)hipGetLastError();
-    hipLaunchKernelGGL(kb_pack, dim3((unsigned)items[0]), blk, 0, stream, v);
-    hipLaunchKernelGGL(kb_local, dim3((unsigned)items[1]), blk, 0, stream, v);
-    hipLaunchKernelGGL(kb_merge, dim3((unsigned)items[2]), small, 0, stream, v);
-    hipLaunchKernelGGL(kb_roots, dim3((unsigned)items[3]), small, 0, stream, v);
-    hipLaunchKernelGGL(kb_rowsum, dim3((unsigned)items[4]), blk, 0, stream, v);
-    hipLaunchKernelGGL(kb_scanblk, dim3((unsigned)items[5]), blk, 0, stream, v);
-    hipLaunchKernelGGL(kb_rowpre, dim3((unsigned)items[6]), blk, 0, stream, v);
-    hipLaunchKernelGGL(kb_canon, dim3((unsigned)items[7]), small, 0, stream, v);
-    hipLaunchKernelGGL(kb_write, dim3((unsigned)items[8]), blk, 0, stream, v);
+    hipLaunchKernelGGL(kb_local, dim3((unsigned)items[0]), blk, 0, stream, v);
+    hipLaunchKernelGGL(kb_merge, dim3((unsigned)items[1]), small, 0, stream, v);
+    hipLaunchKernelGGL(kb_roots, dim3((unsigned)items[2]), small, 0, stream, v);
+    hipLaunchKernelGGL(kb_rowsum, dim3((unsigned)items[3]), blk, 0, stream, v);
+    hipLaunchKernelGGL(kb_scanblk, dim3((unsigned)items[4]), blk, 0, stream, v);
+    hipLaunchKernelGGL(kb_rowpre, dim3((unsigned)items[5]), blk, 0, stream, v);
+    hipLaunchKernelGGL(kb_canon, dim3((unsigned)items[6]), small, 0, stream, v);
+    hipLaunchKernelGGL(kb_write, dim3((unsigned)items[7]), blk, 0, stream, v);
     return hipGetLastError() == hipSuccess ? HK_OK : HK_ERR_HIP;
 }
 

@@ -10,8 +10,8 @@
 // launch one workgroup per item of every job of a batch.
 //
 // Phases (paper correspondence in brackets):
-//   pack    phi -> occupancy words                      [Sec. 2 condition]
-//   local   rules 2/3 on x-runs inside a brick (LDS):   [Sec. 2 rules 1-3,
+//   local   phi -> occupancy words (ballot per row);    [Sec. 2 condition]
+//           rules 2/3 on x-runs inside a brick (LDS):   [Sec. 2 rules 1-3,
 //           components that touch a face shared with     restricted to a brick]
 //           another brick (or a periodic wrap) become
 //           global nodes; the rest are finished clusters
@@ -300,35 +300,35 @@ __device__ __forceinline__ void g_unite(const Geo &g, int a, int b) {
 }
 
 // --------------------------------------------------------------------------
-// phase: pack phi into occupancy words (one workgroup per brick); each wave
-// takes a band of rows, lane j keeps the ballot of the band's j-th row
+// occupancy of one brick, straight from phi: each wave takes a band of
+// rows; lane x loads site x of U rows at once, and one ballot per row turns
+// the 64 sites into the row's word, kept in LDS and stored for the relabel
+// pass
 // --------------------------------------------------------------------------
 
-__device__ __forceinline__ void phase_pack(const Geo &g, int b) {
-    const Brick k = brick_of(g, b);
+__device__ __forceinline__ void load_occupancy(const Geo &g, const Brick &k, int b, LdsBrick &s) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int rpw = (g.R + NW - 1) / NW;
+    const int r0 = wv * rpw, r1 = min(g.R, r0 + rpw);
     constexpr int U = 16;
-    for (int base = wv * rpw; base < min(g.R, (wv + 1) * rpw); base += 64) {
-        const int end = min(min(g.R, (wv + 1) * rpw), base + 64);
-        uint64_t mine = 0;
-        for (int j0 = 0; j0 < 64 && base + j0 < end; j0 += U) {
-            float v[U];
+    for (int base = r0; base < r1; base += U) {
+        float v[U];
 #pragma unroll
-            for (int j = 0; j < U; ++j) {
-                const int r = base + j0 + j;
-                const int yl = r & (g.BY - 1), zl = r >> g.lby;
-                v[j] = 0.0f;
-                if (r < end && yl < k.ey && zl < k.ez && lane < k.ex)
-                    v[j] = g.phi[((int64_t)(k.z0 + zl) * g.ny + (k.y0 + yl)) * g.nx + k.x0 + lane];
-            }
+        for (int j = 0; j < U; ++j) {
+            const int r = base + j;
+            const int yl = r & (g.BY - 1), zl = r >> g.lby;
+            v[j] = 0.0f;
+            if (r < r1 && yl < k.ey && zl < k.ez && lane < k.ex)
+                v[j] = g.phi[((int64_t)(k.z0 + zl) * g.ny + (k.y0 + yl)) * g.nx + k.x0 + lane];
+        }
 #pragma unroll
-            for (int j = 0; j < U; ++j) {
-                const uint64_t m = __ballot(occupied(v[j]));
-                if (lane == j0 + j) mine = m;
+        for (int j = 0; j < U; ++j) {
+            const uint64_t m = __ballot(occupied(v[j]));
+            if (lane == 0 && base + j < r1) {
+                s.occ[base + j] = m;
+                g.occ[(int64_t)b * g.R + base + j] = m;
             }
         }
-        if (base + lane < end) g.occ[(int64_t)b * g.R + base + lane] = mine;
     }
 }
 
@@ -530,10 +530,8 @@ __device__ __forceinline__ void phase_local(const Geo &g, int b, LdsBrick &s) {
     const Brick k = brick_of(g, b);
     const int t = threadIdx.x, row = t / TPR, q = t % TPR;
     const int R = g.R;
-    if (t < R) {
-        s.occ[t] = g.occ[(int64_t)b * R + t];
-        s.rootw[t] = 0ull;
-    }
+    load_occupancy(g, k, b, s);
+    if (t < R) s.rootw[t] = 0ull;
     __syncthreads();
     const CoreOut co = brick_core(g, k, s);
 
@@ -958,7 +956,7 @@ __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
 // store of a phase as a possible write to them.
 // --------------------------------------------------------------------------
 
-constexpr int NPH = 9;  // pack, local, merge, roots, rowsum, scanblk, rowpre, canon, write
+constexpr int NPH = 8;  // local, merge, roots, rowsum, scanblk, rowpre, canon, write
 
 typedef const __attribute__((address_space(4))) Geo ConstGeo;
 typedef const __attribute__((address_space(4))) int32_t ConstI32;

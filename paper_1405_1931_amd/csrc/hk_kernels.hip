@@ -5,8 +5,6 @@
 
 namespace hk {
 
-__global__ __launch_bounds__(WG) void k_pack(Geo g) { phase_pack(g, blockIdx.x); }
-
 __global__ __launch_bounds__(WG) void k_local(Geo g) {
     __shared__ LdsBrick s;
     phase_local(g, blockIdx.x, s);
@@ -41,7 +39,7 @@ __global__ __launch_bounds__(WG) void k_write(Geo g) {
     phase_write(g, blockIdx.x, s);
 }
 
-const char *const kPhaseNames[kPhases] = {"k_pack",   "k_local",  "k_merge", "k_roots", "k_rowsum",
+const char *const kPhaseNames[kPhases] = {"k_local",  "k_merge",  "k_roots", "k_rowsum",
                                           "k_scanblk", "k_rowpre", "k_canon", "k_write"};
 
 hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev) {
@@ -50,24 +48,22 @@ hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev) {
         if (ev) (void)hipEventRecord(ev[i], st);
     };
     mark(0);
-    hipLaunchKernelGGL(k_pack, dim3(g.nb), blk, 0, st, g);
-    mark(1);
     hipLaunchKernelGGL(k_local, dim3(g.nb), blk, 0, st, g);
-    mark(2);
+    mark(1);
     hipLaunchKernelGGL(k_merge, dim3(g.nb), small, 0, st, g);
-    mark(3);
+    mark(2);
     hipLaunchKernelGGL(k_roots, dim3(g.nb), small, 0, st, g);
-    mark(4);
+    mark(3);
     hipLaunchKernelGGL(k_rowsum, dim3(g.nblk), blk, 0, st, g);
-    mark(5);
+    mark(4);
     hipLaunchKernelGGL(k_scanblk, dim3(1), blk, 0, st, g);
-    mark(6);
+    mark(5);
     hipLaunchKernelGGL(k_rowpre, dim3(g.nblk), blk, 0, st, g);
-    mark(7);
+    mark(6);
     hipLaunchKernelGGL(k_canon, dim3(g.nb), small, 0, st, g);
-    mark(8);
+    mark(7);
     hipLaunchKernelGGL(k_write, dim3(g.nb), blk, 0, st, g);
-    mark(9);
+    mark(8);
     return hipGetLastError();
 }
 

@@ -7,10 +7,10 @@
 
 namespace hk {
 
-constexpr int kPhases = 9;
+constexpr int kPhases = 8;
 extern const char *const kPhaseNames[kPhases];
 
-// enqueue the nine single-lattice phases on `st`; when `ev` is non-null,
+// enqueue the eight single-lattice phases on `st`; when `ev` is non-null,
 // ev[0..kPhases] are recorded on `st` before each kernel and after the last
 hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev);
 
