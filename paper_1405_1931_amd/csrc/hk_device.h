@@ -146,16 +146,24 @@ __device__ __forceinline__ int lds_ld(const int32_t *p) {
 __device__ __forceinline__ void lds_st(int32_t *p, int v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ int gl_ld(const int32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ void gl_st(int32_t *p, int v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Wave-uniform values (the row, its word, its run starts, its base address)
+// are made scalar explicitly: the compiler cannot tell that threadIdx.x / 64
+// is the same across a wave, and per-row arithmetic left in vector registers
+// costs a full wave instruction each.
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t wave_uniform64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // exclusive prefix sum over the WG threads of the workgroup; all threads call
 __device__ __forceinline__ int block_excl_scan(int v, int32_t *tmp, int *total) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = wave_uniform(threadIdx.x >> 6);
     int x = v;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -254,25 +262,35 @@ __device__ __forceinline__ void l_unite(const Geo &g, int32_t *par, int a, int b
 // union-find over global nodes: a root is linked (CAS) below the root whose
 // key (linear index of its lowest site) is smaller, so each cluster's final
 // root is the node holding the cluster's lowest site.
+//
+// Parent reads may be served by the XCD's own cache and so be stale: a stale
+// parent is still an ancestor (trees only ever merge), so a find on stale
+// values only takes a longer path.  Writes stay device-coherent: links are
+// CAS on the true entry, and a failed CAS returns the true parent, from
+// which the union carries on, so every retry climbs the true tree.
 // --------------------------------------------------------------------------
+
+__device__ __forceinline__ int nd_ld(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 
 __device__ __forceinline__ int g_find(const Geo &g, int x) {
     int32_t *par = g.npar;
     const int nn = n_nodes(g);
     for (int i = 0; i < GUARD; ++i) {
-        const int p = gl_ld(par + x);
+        const int p = nd_ld(par + x);
         if (p == x) return x;
         if ((unsigned)p >= (unsigned)nn) {
             set_err(g, ERR_RANGE);
             return x;
         }
-        const int gp = gl_ld(par + p);
+        const int gp = nd_ld(par + p);
         if (gp == p) return p;
         if ((unsigned)gp >= (unsigned)nn) {
             set_err(g, ERR_RANGE);
             return p;
         }
-        gl_st(par + x, gp);  // path halving; only non-roots are rewritten
+        gl_st(par + x, gp);  // path halving; only non-roots are rewritten, always to an ancestor
         x = gp;
     }
     set_err(g, ERR_LOOP);
@@ -294,7 +312,13 @@ __device__ __forceinline__ void g_unite(const Geo &g, int a, int b) {
             a = b;
             b = t;
         }
-        if (atomicCAS(g.npar + a, a, b) == a) return;
+        const int old = atomicCAS(g.npar + a, a, b);
+        if (old == a) return;
+        if ((unsigned)old >= (unsigned)nn) {
+            set_err(g, ERR_RANGE);
+            return;
+        }
+        a = old;  // a was linked meanwhile: carry on from its true parent
     }
     set_err(g, ERR_LOOP);
 }
@@ -306,29 +330,51 @@ __device__ __forceinline__ void g_unite(const Geo &g, int a, int b) {
 // pass
 // --------------------------------------------------------------------------
 
-__device__ __forceinline__ void load_occupancy(const Geo &g, const Brick &k, int b, LdsBrick &s) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+constexpr int OCC_U = 16;  // rows a wave has in flight at once
+
+// this wave's band of brick rows: [r0, r1)
+__device__ __forceinline__ void wave_band(const Geo &g, int *r0, int *r1) {
+    const int wv = wave_uniform(threadIdx.x >> 6);
     const int rpw = (g.R + NW - 1) / NW;
-    const int r0 = wv * rpw, r1 = min(g.R, r0 + rpw);
-    constexpr int U = 16;
-    for (int base = r0; base < r1; base += U) {
-        float v[U];
+    *r0 = wv * rpw;
+    *r1 = min(g.R, *r0 + rpw);
+}
+
+// lane x loads site x of rows base .. base+OCC_U-1 (0 outside the lattice)
+__device__ __forceinline__ void fetch_rows(const Geo &g, const Brick &k, int base, int r1, float (&v)[OCC_U]) {
+    const int lane = threadIdx.x & 63;
 #pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const int r = base + j;
-            const int yl = r & (g.BY - 1), zl = r >> g.lby;
-            v[j] = 0.0f;
-            if (r < r1 && yl < k.ey && zl < k.ez && lane < k.ex)
-                v[j] = g.phi[((int64_t)(k.z0 + zl) * g.ny + (k.y0 + yl)) * g.nx + k.x0 + lane];
-        }
+    for (int j = 0; j < OCC_U; ++j) {
+        const int r = base + j;
+        const int yl = r & (g.BY - 1), zl = r >> g.lby;
+        v[j] = 0.0f;
+        if (r < r1 && yl < k.ey && zl < k.ez && lane < k.ex)
+            v[j] = g.phi[((int64_t)(k.z0 + zl) * g.ny + (k.y0 + yl)) * g.nx + k.x0 + lane];
+    }
+}
+
+// one ballot per row: the row's occupancy word, to LDS and to the brick's words
+__device__ __forceinline__ void ballot_rows(const Geo &g, int b, int base, int r1, const float (&v)[OCC_U],
+                                            LdsBrick &s) {
+    const int lane = threadIdx.x & 63;
 #pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const uint64_t m = __ballot(occupied(v[j]));
-            if (lane == 0 && base + j < r1) {
-                s.occ[base + j] = m;
-                g.occ[(int64_t)b * g.R + base + j] = m;
-            }
+    for (int j = 0; j < OCC_U; ++j) {
+        const uint64_t m = __ballot(occupied(v[j]));
+        if (lane == 0 && base + j < r1) {
+            s.occ[base + j] = m;
+            g.occ[(int64_t)b * g.R + base + j] = m;
         }
+    }
+}
+
+// occupancy of a brick, OCC_U rows in flight per wave
+__device__ __forceinline__ void load_occupancy(const Geo &g, const Brick &k, int b, LdsBrick &s) {
+    int r0, r1;
+    wave_band(g, &r0, &r1);
+    for (int base = r0; base < r1; base += OCC_U) {
+        float v[OCC_U];
+        fetch_rows(g, k, base, r1, v);
+        ballot_rows(g, b, base, r1, v, s);
     }
 }
 
@@ -526,11 +572,11 @@ __device__ __forceinline__ int root_of(const LdsBrick &s, int run) {
 // table, the component slot of every run and the face tables
 // --------------------------------------------------------------------------
 
-__device__ __forceinline__ void phase_local(const Geo &g, int b, LdsBrick &s) {
-    const Brick k = brick_of(g, b);
+// After the brick's occupancy is in s.occ: label it, write its nodes,
+// interior components, run slots and face tables.
+__device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b, LdsBrick &s) {
     const int t = threadIdx.x, row = t / TPR, q = t % TPR;
     const int R = g.R;
-    load_occupancy(g, k, b, s);
     if (t < R) s.rootw[t] = 0ull;
     __syncthreads();
     const CoreOut co = brick_core(g, k, s);
@@ -594,7 +640,7 @@ __device__ __forceinline__ void phase_local(const Geo &g, int b, LdsBrick &s) {
     uint16_t *F = g.face + (int64_t)b * g.fstride;
     // y and z face rows, spread over the waves: entry f < ez is row (0, f)
     // of the low y face, then the high y face, the low z face, the high z face
-    const int lane = t & 63, wv = t >> 6;
+    const int lane = t & 63, wv = wave_uniform(t >> 6);
     for (int f = wv; f < 2 * (k.ey + k.ez); f += NW) {
         int yl, zl, sec;
         bool on;
@@ -609,10 +655,10 @@ __device__ __forceinline__ void phase_local(const Geo &g, int b, LdsBrick &s) {
         }
         if (!on) continue;
         const int r = yl + g.BY * zl;
-        const uint64_t w = s.occ[r];
+        const uint64_t w = wave_uniform64(s.occ[r]);
         uint16_t e = NOSITE;
         if ((w >> lane) & 1ull) {
-            const int run = s.rowoff[r] + __popcll(run_starts(w) & mask_le(lane)) - 1;
+            const int run = wave_uniform(s.rowoff[r]) + (int)__popcll(run_starts(w) & mask_le(lane)) - 1;
             const int bidx = -1 - s.par[root_of(s, run)];
             if (bidx >= 0 && bidx < g.cap)
                 e = (uint16_t)bidx;
@@ -644,6 +690,13 @@ __device__ __forceinline__ void phase_local(const Geo &g, int b, LdsBrick &s) {
         }
     }
 }
+
+__device__ __forceinline__ void phase_local(const Geo &g, int b, LdsBrick &s) {
+    const Brick k = brick_of(g, b);
+    load_occupancy(g, k, b, s);
+    local_labels(g, k, b, s);
+}
+
 
 // --------------------------------------------------------------------------
 // phase: merge -- unite nodes across the brick's low x/y/z faces (the high
@@ -854,19 +907,25 @@ __device__ __forceinline__ void phase_canon(const Geo &g, int b) {
 template <bool RUNS_IN_LDS>
 __device__ __forceinline__ void write_rows(const Geo &g, const Brick &k, const LdsBrick &s, int nc,
                                            const uint16_t *L) {
-    const int t = threadIdx.x;
-    const int lane = t & 63, wv = t >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_uniform(threadIdx.x >> 6);
+    const uint64_t bit = 1ull << lane, le = mask_le(lane);
+    const int runmax = g.runcap - 1;
     for (int r = wv; r < g.R; r += NW) {
         const int yl = r & (g.BY - 1), zl = r >> g.lby;
         if (yl >= k.ey || zl >= k.ez) continue;
-        const uint64_t wr = s.occ[r];
+        const uint64_t wr = wave_uniform64(s.occ[r]);
+        const uint64_t st = run_starts(wr);
+        const int off = wave_uniform(s.rowoff[r]) - 1;
+        int32_t *row = g.labels + ((int64_t)(k.z0 + zl) * g.ny + (k.y0 + yl)) * g.nx + k.x0;
         int lab = 0;
-        if ((wr >> lane) & 1ull) {
-            const int run = min(s.rowoff[r] + __popcll(run_starts(wr) & mask_le(lane)) - 1, g.runcap - 1);
+        if (wr & bit) {
+            const int x = off + (int)__popcll(st & le);
+            const int run = x < runmax ? x : runmax;
             const int slot = RUNS_IN_LDS ? s.par[nc + run] : L[run];
             lab = s.par[min(slot, MAXRUNS - 1)];
         }
-        if (lane < k.ex) g.labels[((int64_t)(k.z0 + zl) * g.ny + (k.y0 + yl)) * g.nx + k.x0 + lane] = lab;
+        if (lane < k.ex) row[lane] = lab;
     }
 }
 
