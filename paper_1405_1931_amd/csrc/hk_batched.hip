@@ -36,9 +36,10 @@ __global__ __launch_bounds__(WG) void kb_local(GroupView v) {
 }
 
 __global__ __launch_bounds__(WG_NODES) void kb_merge(GroupView v) {
+    __shared__ MergeLds m;
     int i;
     const Geo &g = locate(v, 1, blockIdx.x, &i);
-    phase_merge(g, i);
+    phase_merge(g, i, m);
 }
 
 __global__ __launch_bounds__(WG_NODES) void kb_roots(GroupView v) {

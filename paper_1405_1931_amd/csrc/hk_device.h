@@ -701,50 +701,108 @@ __device__ __forceinline__ void phase_local(const Geo &g, int b, LdsBrick &s) {
 // --------------------------------------------------------------------------
 // phase: merge -- unite nodes across the brick's low x/y/z faces (the high
 // faces are the low faces of the next bricks; wraps pair brick 0 with the
-// last brick of a periodic axis)
+// last brick of a periodic axis).
+//
+// The three low faces are cut into chunks of 64 consecutive face sites (one
+// x row of a y or z face, or 64 rows of the x face), one site per lane, so
+// the check "the previous site along the face already joined the same two
+// components" is a shuffle.  The waves read their chunks' face entries
+// several chunks at a time and append the pairs to unite to an LDS list; the
+// unions are then spread evenly over the workgroup.
 // --------------------------------------------------------------------------
 
-__device__ __forceinline__ void phase_merge(const Geo &g, int b) {
+constexpr int MERGE_CAP = 1024;  // pairs held in LDS; further pairs are united where found
+constexpr int MERGE_U = 3;       // chunks per wave read together
+
+struct MergeLds {
+    int2 pair[MERGE_CAP];
+    int count;
+};
+
+__device__ __forceinline__ void phase_merge(const Geo &g, int b, MergeLds &m) {
     const Brick k = brick_of(g, b);
-    const int t = threadIdx.x, nt = blockDim.x;
-    const int R = g.R;
+    const int lane = threadIdx.x & 63;
+    const int wv = wave_uniform(threadIdx.x >> 6), nw = blockDim.x >> 6;
+    if (threadIdx.x == 0) m.count = 0;
+    __syncthreads();
     const uint16_t *F = g.face + (int64_t)b * g.fstride;
-    if (k.hxl) {
-        const int nbb = k.bx > 0 ? b - 1 : b + (g.nbx - 1);
-        const uint16_t *G = g.face + (int64_t)nbb * g.fstride;
-        for (int r = t; r < R; r += nt) {
-            const int yl = r & (g.BY - 1), zl = r >> g.lby;
-            if (yl >= k.ey || zl >= k.ez) continue;
-            const uint16_t a = F[f_xlo(g) + r], c = G[f_xhi(g) + r];
-            if (a == NOSITE || c == NOSITE) continue;
-            if (yl > 0 && F[f_xlo(g) + r - 1] != NOSITE && G[f_xhi(g) + r - 1] != NOSITE) continue;
-            g_unite(g, b * g.cap + a, nbb * g.cap + c);
+    const int bxn = k.bx > 0 ? b - 1 : b + (g.nbx - 1);
+    const int byn = k.by > 0 ? b - g.nbx : b + (g.nby - 1) * g.nbx;
+    const int bzn = k.bz > 0 ? b - g.nbx * g.nby : b + (g.nbz - 1) * g.nbx * g.nby;
+    const int cx = k.hxl ? (g.R + 63) >> 6 : 0, cy = k.hyl ? g.BZ : 0, cz = k.hzl ? g.BY : 0;
+    const int nch = cx + cy + cz;
+    for (int c0 = wv; c0 < nch; c0 += nw * MERGE_U) {
+        uint16_t fa[MERGE_U], fc[MERGE_U];
+        bool pre[MERGE_U];
+        int nbb[MERGE_U];
+#pragma unroll
+        for (int u = 0; u < MERGE_U; ++u) {
+            const int c = c0 + u * nw;  // wave-uniform
+            fa[u] = fc[u] = NOSITE;
+            pre[u] = false;
+            nbb[u] = b;
+            if (c >= nch) continue;
+            const uint16_t *Fs, *Gs;
+            int e;
+            bool valid;
+            if (c < cx) {  // x face: entry = brick row
+                e = c * 64 + lane;
+                const int yl = e & (g.BY - 1), zl = e >> g.lby;
+                valid = e < g.R && yl < k.ey && zl < k.ez;
+                nbb[u] = bxn;
+                Fs = F + f_xlo(g);
+                Gs = g.face + (int64_t)bxn * g.fstride + f_xhi(g);
+                // row e-1 (same plane) is in lane-1, except at lane 0 of a
+                // chunk that starts inside a y row (BY > 64)
+                pre[u] = valid && yl > 0 && lane == 0;
+            } else if (c < cx + cy) {  // low y face: entry = zl * 64 + x
+                const int zl = c - cx;
+                e = zl * 64 + lane;
+                valid = zl < k.ez && lane < k.ex;
+                nbb[u] = byn;
+                Fs = F + f_ylo(g);
+                Gs = g.face + (int64_t)byn * g.fstride + f_yhi(g);
+            } else {  // low z face: entry = yl * 64 + x
+                const int yl = c - cx - cy;
+                e = yl * 64 + lane;
+                valid = yl < k.ey && lane < k.ex;
+                nbb[u] = bzn;
+                Fs = F + f_zlo(g);
+                Gs = g.face + (int64_t)bzn * g.fstride + f_zhi(g);
+            }
+            if (valid) {
+                fa[u] = Fs[e];
+                fc[u] = Gs[e];
+                if (pre[u]) pre[u] = Fs[e - 1] != NOSITE && Gs[e - 1] != NOSITE;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < MERGE_U; ++u) {
+            const int c = c0 + u * nw;
+            if (c >= nch) continue;
+            const bool both = fa[u] != NOSITE && fc[u] != NOSITE;
+            // was the previous site along the face a pair too?
+            const int up = __shfl_up((int)both, 1, 64);
+            bool prev;
+            if (c < cx) {
+                const int e = c * 64 + lane;
+                prev = lane > 0 ? (up != 0 && (e & (g.BY - 1)) > 0) : pre[u];
+            } else {
+                prev = lane > 0 && up != 0;
+            }
+            if (both && !prev) {
+                const int na = b * g.cap + fa[u], nc = nbb[u] * g.cap + fc[u];
+                const int i = atomicAdd(&m.count, 1);
+                if (i < MERGE_CAP)
+                    m.pair[i] = make_int2(na, nc);
+                else
+                    g_unite(g, na, nc);
+            }
         }
     }
-    if (k.hyl) {
-        const int nbb = k.by > 0 ? b - g.nbx : b + (g.nby - 1) * g.nbx;
-        const uint16_t *G = g.face + (int64_t)nbb * g.fstride;
-        for (int e = t; e < 64 * k.ez; e += nt) {
-            const int x = e & 63;
-            if (x >= k.ex) continue;
-            const uint16_t a = F[f_ylo(g) + e], c = G[f_yhi(g) + e];
-            if (a == NOSITE || c == NOSITE) continue;
-            if (x > 0 && F[f_ylo(g) + e - 1] != NOSITE && G[f_yhi(g) + e - 1] != NOSITE) continue;
-            g_unite(g, b * g.cap + a, nbb * g.cap + c);
-        }
-    }
-    if (k.hzl) {
-        const int nbb = k.bz > 0 ? b - g.nbx * g.nby : b + (g.nbz - 1) * g.nbx * g.nby;
-        const uint16_t *G = g.face + (int64_t)nbb * g.fstride;
-        for (int e = t; e < 64 * k.ey; e += nt) {
-            const int x = e & 63;
-            if (x >= k.ex) continue;
-            const uint16_t a = F[f_zlo(g) + e], c = G[f_zhi(g) + e];
-            if (a == NOSITE || c == NOSITE) continue;
-            if (x > 0 && F[f_zlo(g) + e - 1] != NOSITE && G[f_zhi(g) + e - 1] != NOSITE) continue;
-            g_unite(g, b * g.cap + a, nbb * g.cap + c);
-        }
-    }
+    __syncthreads();
+    const int n = min(m.count, MERGE_CAP);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) g_unite(g, m.pair[i].x, m.pair[i].y);
 }
 
 // --------------------------------------------------------------------------

@@ -10,7 +10,10 @@ __global__ __launch_bounds__(WG) void k_local(Geo g) {
     phase_local(g, blockIdx.x, s);
 }
 
-__global__ __launch_bounds__(WG_NODES) void k_merge(Geo g) { phase_merge(g, blockIdx.x); }
+__global__ __launch_bounds__(WG_NODES) void k_merge(Geo g) {
+    __shared__ MergeLds m;
+    phase_merge(g, blockIdx.x, m);
+}
 
 __global__ __launch_bounds__(WG_NODES) void k_roots(Geo g) {
     __shared__ int32_t hash[2 * HT];
