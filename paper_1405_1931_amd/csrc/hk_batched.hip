@@ -46,7 +46,7 @@ __global__ __launch_bounds__(WG_NODES) void kb_roots(GroupView v) {
     __shared__ int32_t hash[2 * HT];
     int i;
     const Geo &g = locate(v, 2, blockIdx.x, &i);
-    phase_roots(g, i, hash);
+    phase_roots(g, i, 1, hash);
 }
 
 __global__ __launch_bounds__(WG) void kb_rowsum(GroupView v) {

@@ -323,6 +323,52 @@ __device__ __forceinline__ void g_unite(const Geo &g, int a, int b) {
     set_err(g, ERR_LOOP);
 }
 
+// Roots of two nodes at once: the two pointer chases advance in lockstep,
+// so their loads are in flight together (same halving rule as g_find).
+__device__ __forceinline__ void g_find2(const Geo &g, int &x, int &y) {
+    int32_t *par = g.npar;
+    const int nn = n_nodes(g);
+    bool dx = false, dy = false;
+    for (int i = 0; i < GUARD; ++i) {
+        if (dx && dy) return;
+        const int px = dx ? x : nd_ld(par + x);
+        const int py = dy ? y : nd_ld(par + y);
+        if ((unsigned)px >= (unsigned)nn || (unsigned)py >= (unsigned)nn) {
+            set_err(g, ERR_RANGE);
+            return;
+        }
+        const int gx = (dx || px == x) ? px : nd_ld(par + px);
+        const int gy = (dy || py == y) ? py : nd_ld(par + py);
+        if ((unsigned)gx >= (unsigned)nn || (unsigned)gy >= (unsigned)nn) {
+            set_err(g, ERR_RANGE);
+            return;
+        }
+        if (!dx) {
+            if (px == x) {
+                dx = true;
+            } else if (gx == px) {
+                x = px;
+                dx = true;
+            } else {
+                gl_st(par + x, gx);
+                x = gx;
+            }
+        }
+        if (!dy) {
+            if (py == y) {
+                dy = true;
+            } else if (gy == py) {
+                y = py;
+                dy = true;
+            } else {
+                gl_st(par + y, gy);
+                y = gy;
+            }
+        }
+    }
+    set_err(g, ERR_LOOP);
+}
+
 // --------------------------------------------------------------------------
 // occupancy of one brick, straight from phi: each wave takes a band of
 // rows; lane x loads site x of U rows at once, and one ballot per row turns
@@ -822,7 +868,9 @@ constexpr int HT_BITS = 11;
 constexpr int HT = 1 << HT_BITS;  // hash slots: keys in hash[0, HT), sums in hash[HT, 2 HT)
 static_assert(2 * HT <= MAXRUNS, "the hash must fit in the run array of LdsBrick");
 
-__device__ __forceinline__ void phase_roots(const Geo &g, int b, int32_t *hash) {
+// Bricks b0 .. b0 + nbr - 1 share the LDS hash, so a root that many bricks
+// reach (the spanning cluster's) receives one global add per group of bricks.
+__device__ __forceinline__ void phase_roots(const Geo &g, int b0, int nbr, int32_t *hash) {
     int32_t *hkey = hash, *hval = hash + HT;
     const int nt = blockDim.x;
     for (int i = threadIdx.x; i < HT; i += nt) {
@@ -830,32 +878,43 @@ __device__ __forceinline__ void phase_roots(const Geo &g, int b, int32_t *hash) 
         hval[i] = 0;
     }
     __syncthreads();
-    const int cnt = g.bcount[b];
-    for (int i = threadIdx.x; i < cnt; i += nt) {
-        const int n = b * g.cap + i;
-        const int r = g_find(g, n);
-        // position of the root's key site: word index << 6 | bit
-        const int lr = g.nlpos[r];
-        g.nrootpos[n] = (((int64_t)(r / g.cap) * g.R + min(lr >> 6, g.R - 1)) << 6) | (lr & 63);
-        if (r == n) {
-            if ((lr >> 6) < g.R)
-                atomicOr((unsigned long long *)(g.root + (int64_t)b * g.R + (lr >> 6)), 1ull << (lr & 63));
-            else
-                set_err(g, ERR_RANGE);
-        } else {
-            const int add = g.nsize[n];
-            int h = (int)(((uint32_t)r * 2654435761u) >> (32 - HT_BITS));
-            bool done = false;
-            for (int probe = 0; probe < 64; ++probe) {
-                const int old = atomicCAS(hkey + h, -1, r);
-                if (old == -1 || old == r) {
-                    atomicAdd(hval + h, add);
-                    done = true;
-                    break;
+    for (int b = b0; b < b0 + nbr && b < g.nb; ++b) {
+        const int cnt = g.bcount[b];
+        // two nodes per thread and step: i and i + nt
+        for (int i0 = threadIdx.x; i0 < cnt; i0 += 2 * nt) {
+            const int n0 = b * g.cap + i0;
+            const bool two = i0 + nt < cnt;
+            const int n1 = two ? n0 + nt : n0;
+            int r0 = n0, r1 = n1;
+            g_find2(g, r0, r1);
+    #pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (u == 1 && !two) break;
+                const int n = u ? n1 : n0, r = u ? r1 : r0;
+                // position of the root's key site: word index << 6 | bit
+                const int lr = g.nlpos[r];
+                g.nrootpos[n] = (((int64_t)(r / g.cap) * g.R + min(lr >> 6, g.R - 1)) << 6) | (lr & 63);
+                if (r == n) {
+                    if ((lr >> 6) < g.R)
+                        atomicOr((unsigned long long *)(g.root + (int64_t)b * g.R + (lr >> 6)), 1ull << (lr & 63));
+                    else
+                        set_err(g, ERR_RANGE);
+                } else {
+                    const int add = g.nsize[n];
+                    int h = (int)(((uint32_t)r * 2654435761u) >> (32 - HT_BITS));
+                    bool done = false;
+                    for (int probe = 0; probe < 64; ++probe) {
+                        const int old = atomicCAS(hkey + h, -1, r);
+                        if (old == -1 || old == r) {
+                            atomicAdd(hval + h, add);
+                            done = true;
+                            break;
+                        }
+                        h = (h + 1) & (HT - 1);
+                    }
+                    if (!done) atomicAdd(g.nsize + r, add);
                 }
-                h = (h + 1) & (HT - 1);
             }
-            if (!done) atomicAdd(g.nsize + r, add);
         }
     }
     __syncthreads();
@@ -925,25 +984,45 @@ __device__ __forceinline__ void phase_rowpre(const Geo &g, int blk, int32_t *tmp
 
 __device__ __forceinline__ void phase_canon(const Geo &g, int b) {
     const int cnt = g.bcount[b];
+    const int nt = blockDim.x;
     const int64_t kmax = (n_sites(g) + 1) / 2;
     const int64_t words = (int64_t)g.nb * g.R;
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-        const int n = b * g.cap + i;
-        const int64_t pos = g.nrootpos[n];
-        const int64_t wi = pos >> 6;
-        if (wi < 0 || wi >= words) {
-            set_err(g, ERR_RANGE);
-            continue;
+    // two nodes per thread and step, loads of both in flight together
+    for (int i0 = threadIdx.x; i0 < cnt; i0 += 2 * nt) {
+        const bool two = i0 + nt < cnt;
+        int64_t pos[2], wi[2];
+        int n[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            n[u] = b * g.cap + i0 + (u && two ? nt : 0);
+            pos[u] = g.nrootpos[n[u]];
+            wi[u] = pos[u] >> 6;
         }
-        const int rank = g.wpre[wi] + __popcll(g.root[wi] & mask_lt((int)(pos & 63)));
-        g.ncanon[n] = rank + 1;
-        const int lp = g.nlpos[n];
-        // this node holds the cluster's key site: it is the root
-        if (g.sizes && wi == (int64_t)b * g.R + min(lp >> 6, g.R - 1) && (pos & 63) == (lp & 63)) {
-            if (rank >= 0 && (int64_t)rank < kmax)
-                g.sizes[rank] = g.nsize[n];
-            else
+        uint64_t rw[2];
+        int wp[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const bool ok = wi[u] >= 0 && wi[u] < words;
+            rw[u] = ok ? g.root[wi[u]] : 0ull;
+            wp[u] = ok ? g.wpre[wi[u]] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (u == 1 && !two) break;
+            if (wi[u] < 0 || wi[u] >= words) {
                 set_err(g, ERR_RANGE);
+                continue;
+            }
+            const int rank = wp[u] + __popcll(rw[u] & mask_lt((int)(pos[u] & 63)));
+            g.ncanon[n[u]] = rank + 1;
+            const int lp = g.nlpos[n[u]];
+            // this node holds the cluster's key site: it is the root
+            if (g.sizes && wi[u] == (int64_t)b * g.R + min(lp >> 6, g.R - 1) && (pos[u] & 63) == (lp & 63)) {
+                if (rank >= 0 && (int64_t)rank < kmax)
+                    g.sizes[rank] = g.nsize[n[u]];
+                else
+                    set_err(g, ERR_RANGE);
+            }
         }
     }
 }

@@ -15,9 +15,11 @@ __global__ __launch_bounds__(WG_NODES) void k_merge(Geo g) {
     phase_merge(g, blockIdx.x, m);
 }
 
+constexpr int ROOTS_BRICKS = 4;  // bricks per workgroup of the roots phase
+
 __global__ __launch_bounds__(WG_NODES) void k_roots(Geo g) {
     __shared__ int32_t hash[2 * HT];
-    phase_roots(g, blockIdx.x, hash);
+    phase_roots(g, blockIdx.x * ROOTS_BRICKS, ROOTS_BRICKS, hash);
 }
 
 __global__ __launch_bounds__(WG) void k_rowsum(Geo g) {
@@ -55,7 +57,7 @@ hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev) {
     mark(1);
     hipLaunchKernelGGL(k_merge, dim3(g.nb), small, 0, st, g);
     mark(2);
-    hipLaunchKernelGGL(k_roots, dim3(g.nb), small, 0, st, g);
+    hipLaunchKernelGGL(k_roots, dim3((g.nb + ROOTS_BRICKS - 1) / ROOTS_BRICKS), small, 0, st, g);
     mark(3);
     hipLaunchKernelGGL(k_rowsum, dim3(g.nblk), blk, 0, st, g);
     mark(4);
