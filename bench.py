@@ -257,6 +257,57 @@ def summarize_pmc(fetch_dir, write_dir, kernel, tag, calib_bytes=1 << 30):
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps(out))
+    traffic_table(fetch_dir, write_dir, tag, calib_bytes)
+
+
+def traffic_table(fetch_dir, write_dir, tag, calib_bytes):
+    """profiles/hbm_traffic_<tag>.txt: scaled HBM bytes and durations of every
+    kernel of the path in the two counter runs."""
+    import csv
+    import glob
+
+    rows = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    if r["Counter_Name"] != counter:
+                        continue
+                    e = rows.setdefault((counter, int(r["Dispatch_Id"])), {})
+                    e["name"] = r["Kernel_Name"].split("(")[0]
+                    e["bytes"] = float(r["Counter_Value"]) * 1024.0
+                    e["us"] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+    fac = {}
+    for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+        cal = max(v["bytes"] for (c, _), v in rows.items() if c == counter and "copyBuffer" in v["name"])
+        fac[counter] = calib_bytes / cal
+    per = {}
+    for (counter, _), v in sorted(rows.items(), key=lambda kv: kv[0][1]):
+        if not v["name"].startswith("hk::"):
+            continue
+        e = per.setdefault(v["name"][4:], {"rd": 0.0, "wr": 0.0, "us": []})
+        e["rd" if counter == "FETCH_SIZE" else "wr"] += v["bytes"] * fac[counter] / 1e9
+        e["us"].append(v["us"])
+    lines = [f"# HBM traffic per kernel, hk_label, workload {tag}", "",
+             "commands (from /tmp with TMPDIR=/tmp on the MI355X box; one counter per run):", "",
+             f"    rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fetch_dir} -o run -- python3 bench.py "
+             "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-profile --calib-copy",
+             f"    rocprofv3 --pmc WRITE_SIZE --output-format csv -d {write_dir} -o run -- python3 bench.py "
+             "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-profile --calib-copy",
+             f"    python bench.py --summarize-pmc {fetch_dir} {write_dir} <kernel> {tag}", "",
+             f"calibration: a {calib_bytes / 2**30:.0f} GiB device copy reads FETCH_SIZE "
+             f"{1 / fac['FETCH_SIZE']:.4f}x and WRITE_SIZE {1 / fac['WRITE_SIZE']:.4f}x its size; the counts below are "
+             f"scaled by {fac['FETCH_SIZE']:.4f} (fetch) and {fac['WRITE_SIZE']:.4f} (write).", "",
+             f"{'kernel':<12} {'read_GB':>9} {'write_GB':>9} {'total_GB':>9} {'us':>9} {'TB/s':>7}"]
+    tot = 0.0
+    for name, e in per.items():
+        us = sum(e["us"]) / len(e["us"])
+        t = e["rd"] + e["wr"]
+        tot += t
+        lines.append(f"{name:<12} {e['rd']:>9.3f} {e['wr']:>9.3f} {t:>9.3f} {us:>9.1f} {t / us * 1e3 if us else 0:>7.2f}")
+    lines.append(f"{'all':<12} {'':>9} {'':>9} {tot:>9.3f}")
+    with open(os.path.join(PROFILES, f"hbm_traffic_{tag}.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
 
 
 def main():
