@@ -245,6 +245,38 @@ def _shell_forms(cap, thickness, dx, dy, dz):
     return fo, fi
 
 
+I0 = -1.0  # proximity value of the sites far from every membrane
+
+
+def capsule_proximity(shape, caps, thickness, periodic=(False, False, True), i0=I0):
+    """Proximity field of the capsule shells, as in the Sec. 6 construction:
+    every site far from a membrane keeps ``i0``; a shell site gets a value in
+    (-0.5, 0.5) whose sign says on which side of the membrane it lies --
+    negative towards the capsule interior, positive towards the outside.
+    The membrane is the mid-surface of the shell, ``f_m = 1`` with
+    ``f_m = sum (u_k / (a_k - thickness / 2))^2``; the value is
+    ``0.05 + 0.4 |tanh(f_m - 1)|`` with the sign of ``f_m - 1`` (never 0).
+    The shell sites are exactly the ``phi = -1`` sites of ``capsules``."""
+    nz, ny, nx = shape
+    out = np.full((nz, ny, nx), F32(i0), dtype=F32)
+    for cap in caps:
+        r = float(cap.axes.max()) + 1.0
+        xi, dx = _axis_window(cap.centre[0], r, nx, periodic[0])
+        yi, dy = _axis_window(cap.centre[1], r, ny, periodic[1])
+        zi, dz = _axis_window(cap.centre[2], r, nz, periodic[2])
+        fo, fi = _shell_forms(cap, thickness, dx, dy, dz)
+        shell = (fo <= 1.0) & (fi > 1.0)
+        D = np.stack(np.broadcast_arrays(dx[None, None, :], dy[None, :, None], dz[:, None, None]), axis=-1)
+        u = D @ cap.rot
+        fm = np.sum((u / (cap.axes - thickness / 2.0)) ** 2, axis=-1) - 1.0
+        val = (0.05 + 0.4 * np.abs(np.tanh(fm))) * np.where(fm < 0.0, -1.0, 1.0)
+        sub = np.ix_(zi, yi, xi)
+        blk = out[sub]
+        blk[shell] = val[shell].astype(F32)
+        out[sub] = blk
+    return out
+
+
 def capsule_interior_counts(shape, caps, thickness, periodic=(False, False, True)):
     """Number of lattice sites with f_i <= 1 for each capsule (the interior
     pocket sizes a correct labelling must report)."""
@@ -294,6 +326,16 @@ def config(cid: int, scale: int = 1):
         phi, _ = capsules(shape, caps, 6.0, 15.0, 2.0, seed=4)
         return phi, 4
     raise ValueError(f"config {cid} is not a single lattice")
+
+
+def capsule_config(scale: int = 1):
+    """Config 4 with its proximity field: ``(phi, I, mask)``, where phi > 0
+    exactly on the sites that kept I0 (the cluster sites of the HK pass) and
+    I is signed on the membrane sites (Sec. 6)."""
+    shape = (512 // scale, 256 // scale, 256 // scale)
+    caps = max(1, round(300 / scale ** 3))
+    phi, cl = capsules(shape, caps, 6.0, 15.0, 2.0, seed=4)
+    return phi, capsule_proximity(shape, cl, 2.0), 4
 
 
 @dataclass
