@@ -14,7 +14,7 @@ import oracle
 from oracle import classify as C
 from paper_1405_1931_amd import workloads as W
 
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "classify")
 
 
 def load_fixture(name):
@@ -75,7 +75,7 @@ def cluster_field(I):
     return np.where(I == np.float32(W.I0), np.float32(1), np.float32(-1)).astype(np.float32)
 
 
-@pytest.mark.parametrize("name", ["classify_2d.txt", "classify_row.txt"])
+@pytest.mark.parametrize("name", ["plane_ring.txt", "row_ties.txt"])
 def test_hand_worked_fixtures(name):
     I, cases = load_fixture(name)
     for case in cases:
