@@ -11,7 +11,8 @@ dominant kernel (algorithmic bytes over its live-measured average duration,
 HIP events on the launch stream), the oracle timed on a bounded slab of the
 same workload on the host cores, and the batched-vs-per-lattice comparison
 on the 256-lattice stream, plus the same stream through the continuous-
-batching server (closed loop and Poisson arrivals with p50/p99 latency).
+batching server (closed loop and Poisson arrivals with p50/p99 latency),
+and the interior/exterior decision of Sec. 6 on the capsule workload.
 
 ``--summarize-pmc`` turns two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE)
 of ``bench.py --calib-copy`` into the traffic figure of the roofline.
@@ -209,6 +210,59 @@ def bench_served(hk, torch, bufs, capacity_jobs_s, runs=4, slots=3, max_batch=64
     return out
 
 
+def bench_classify(hk, torch, reps=20):
+    """Config 4 (capsules 256x256x512, z periodic): hk_label on the sites that
+    kept I0, then the interior/exterior decision (Sec. 6).  Times the decision
+    alone (its three kernels, HIP events on the launch stream); algorithmic
+    bytes = labels and I read once (8 B/site) + neg, pos, inside written
+    (17 B/cluster)."""
+    import numpy as np
+
+    from paper_1405_1931_amd import workloads as W
+
+    phi_np, I_np, mask = W.capsule_config()
+    phi = torch.from_numpy(phi_np).cuda()
+    I = torch.from_numpy(I_np).cuda()
+    nz, ny, nx = phi.shape
+    n = phi.numel()
+    labels = torch.empty_like(phi, dtype=torch.int32)
+    kbuf = torch.zeros(1, dtype=torch.int64, device="cuda")
+    cap = max(1, hk.max_clusters(nx, ny, nz))
+    sizes = torch.empty(cap, dtype=torch.int64, device="cuda")
+    neg = torch.empty(cap, dtype=torch.int64, device="cuda")
+    pos = torch.empty(cap, dtype=torch.int64, device="cuda")
+    inside = torch.empty(cap, dtype=torch.int8, device="cuda")
+    hk.label_into(phi, mask, labels, kbuf, sizes)
+    for _ in range(3):
+        hk.classify_into(I, labels, kbuf, mask, neg, pos, inside)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        hk.classify_into(I, labels, kbuf, mask, neg, pos, inside)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    k = int(kbuf.item())
+    ins = inside[:k].cpu().numpy()
+    alg = 8 * n + 17 * k
+    out = {"workload": f"capsules {nx}x{ny}x{nz} mask {mask} ({k - 1} capsules)", "ms": round(ms, 4),
+           "gsites_per_s": round(n / ms / 1e6, 2), "clusters": k,
+           "interiors": int((ins == 1).sum()), "exteriors": int((ins == 0).sum()), "undecided": int((ins == -1).sum()),
+           "roofline": {"bound": "hbm", "algorithmic_bytes": alg, "achieved": round(alg / ms / 1e6, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)}}
+    from oracle import classify as C
+
+    lab_np = labels.cpu().numpy()
+    t0 = time.perf_counter()
+    C.classify(I_np, lab_np, k, mask)
+    dt = time.perf_counter() - t0
+    out["cpu_baseline"] = {"value": round(n / dt / 1e9, 4), "unit": "Gsites/s", "cores": 1, "kind": "oracle",
+                           "sample": f"whole lattice ({n} sites), numpy oracle, {dt:.2f} s"}
+    assert hk.device_error() == 0
+    return out
+
+
 def calibration_copy(torch, nbytes=1 << 30):
     """One plain device copy of `nbytes` (read nbytes + write nbytes), for
     scaling the HBM byte counters of a counter run."""
@@ -321,6 +375,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
     ap.add_argument("--no-served", action="store_true")
+    ap.add_argument("--no-classify", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run one 1 GiB device copy (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "TAG"),
                     help="write profiles/traffic_<KERNEL>_<TAG>.json from two rocprofv3 --pmc runs and exit")
@@ -433,6 +488,10 @@ def main():
             result["served"] = served
             log(f"served: {served}")
         del bufs
+    if not args.no_classify:
+        torch.cuda.empty_cache()
+        result["classify"] = bench_classify(hk, torch)
+        log(f"classify: {result['classify']}")
     if not args.no_cpu_baseline:
         planes = min(args.cpu_planes, edge)
         result["cpu_baseline"] = cpu_baseline(phi_np, mask, planes)

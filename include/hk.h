@@ -94,6 +94,32 @@ typedef struct {
  */
 int hk_label_batched(const hk_job *jobs, int32_t n_jobs, hipStream_t stream);
 
+/*
+ * hk_classify: Sec. 6, last step of the detection of capsule interiors --
+ * the HK pass has labelled the sites that kept the far-field proximity
+ * value (labels, from hk_label on the same lattice: 0 = membrane site,
+ * 1..K = cluster); each cluster is now judged by the proximity values of
+ * the membrane sites around it.
+ *   I            [nz][ny][nx] float32, device, read only: proximity value,
+ *                negative on the interior side of a membrane, positive on
+ *                the exterior side (read only at sites with label 0)
+ *   labels       [nz][ny][nx] int32, device, read only
+ *   n_clusters   one int64, device: K (as hk_label wrote it; read on the
+ *                device, so no host synchronisation is needed in between)
+ *   neg, pos     int64, device, out: for k = 1..K, the number of border
+ *                pairs of cluster k -- face-adjacent (cluster site, label-0
+ *                site) pairs, wrapping on the periodic axes, one pair on a
+ *                periodic axis of length 2 -- whose I is < 0 / > 0; the
+ *                sign is taken on the bits (denormals count, +-0 and NaN
+ *                count for neither side)
+ *   inside       int8, device, out: 1 if neg > pos (interior), 0 if
+ *                pos > neg (exterior), -1 on a tie (or no border at all)
+ * neg, pos and inside must hold hk_max_clusters(nx, ny, nz) entries;
+ * entries >= K are left untouched.  Errors as for hk_label.
+ */
+int hk_classify(const float *I, const int32_t *labels, int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask,
+                const int64_t *n_clusters, int64_t *neg, int64_t *pos, int8_t *inside, hipStream_t stream);
+
 /* ceil(nx*ny*nz / 2): the Sec. 3 bound on the number of clusters, i.e. the
  * capacity `sizes` must have.  0 for invalid edges. */
 int64_t hk_max_clusters(int32_t nx, int32_t ny, int32_t nz);

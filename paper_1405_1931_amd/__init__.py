@@ -167,6 +167,36 @@ def set_brick_for_shape(nx, ny, nz, by, bz):
     _lib.check(_lib.load().hk_set_brick_for_shape(nx, ny, nz, by, bz), "hk_set_brick_for_shape")
 
 
+def classify_into(I, labels, n_clusters, periodic, neg, pos, inside, stream=None):
+    """Enqueue the interior/exterior decision (no synchronisation); output
+    tensors hold max_clusters entries."""
+    import torch
+
+    _check_phi(I)
+    if labels.dtype != torch.int32 or labels.shape != I.shape or not labels.is_contiguous():
+        raise ValueError("labels must be a contiguous int32 tensor shaped like I")
+    nz, ny, nx = I.shape
+    rc = _lib.load().hk_classify(I.data_ptr(), labels.data_ptr(), nx, ny, nz, mask_of(periodic),
+                                 n_clusters.data_ptr(), neg.data_ptr(), pos.data_ptr(), inside.data_ptr(),
+                                 _stream_handle(stream))
+    _lib.check(rc, "hk_classify")
+
+
+def classify(I, labels, n_clusters, periodic=0, stream=None):
+    """(neg, pos, inside)[:K] of every cluster of `labels` (hk_label output on
+    the same lattice; n_clusters its device K tensor)."""
+    import torch
+
+    nz, ny, nx = I.shape
+    cap = max(1, max_clusters(nx, ny, nz))
+    neg = torch.empty(cap, dtype=torch.int64, device=I.device)
+    pos = torch.empty(cap, dtype=torch.int64, device=I.device)
+    inside = torch.empty(cap, dtype=torch.int8, device=I.device)
+    classify_into(I, labels, n_clusters, periodic, neg, pos, inside, stream=stream)
+    k = int(n_clusters.item())
+    return neg[:k], pos[:k], inside[:k]
+
+
 def autotune(phi, periodic=0, reps: int = 3, stream=None):
     """Time every candidate brick shape on this lattice and install the
     fastest for its size bucket; returns (by, bz, ms)."""
