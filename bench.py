@@ -263,6 +263,59 @@ def bench_classify(hk, torch, reps=20):
     return out
 
 
+def bench_droplets(hk, torch, reps=50, r_max=40.0, n_bins=80):
+    """Config 2 (droplets in 512^3, periodic): hk_label, then the droplet-size
+    statistics (Sec. 5) of its sizes.  Times the statistics alone and label +
+    statistics as one pass (HIP events on the launch stream).  The statistics
+    read 8 B per cluster: with a few thousand clusters they are bound by
+    launch latency, not by HBM."""
+    from paper_1405_1931_amd import workloads as W
+
+    phi_np, mask = W.config(2)
+    phi = torch.from_numpy(phi_np).cuda()
+    nz, ny, nx = phi.shape
+    n = phi.numel()
+    labels = torch.empty_like(phi, dtype=torch.int32)
+    kbuf = torch.zeros(1, dtype=torch.int64, device="cuda")
+    sizes = torch.empty(max(1, hk.max_clusters(nx, ny, nz)), dtype=torch.int64, device="cuda")
+    hist = torch.empty(n_bins, dtype=torch.int64, device="cuda")
+    counts = torch.empty(2, dtype=torch.int64, device="cuda")
+    sums = torch.empty(3, dtype=torch.float64, device="cuda")
+
+    def stats():
+        hk.droplet_stats_into(sizes, kbuf, 1, r_max, n_bins, hist, counts, sums)
+
+    def both():
+        hk.label_into(phi, mask, labels, kbuf, sizes)
+        stats()
+
+    out = {"workload": f"droplets {nx}x{ny}x{nz} mask {mask}, r_max {r_max}, {n_bins} bins"}
+    for name, fn in (("stats", stats), ("label_and_stats", both)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"{name}_ms"] = round(e0.elapsed_time(e1) / reps, 4)
+    k = int(kbuf.item())
+    out["clusters"] = k
+    out["label_and_stats_gsites_per_s"] = round(n / out["label_and_stats_ms"] / 1e6, 2)
+    c = counts.tolist()
+    sm = sums.tolist()
+    out["count"], out["mean_radius"] = c[0], round(sm[0] / max(1, c[0]), 4)
+    from oracle import droplets as D
+
+    s_np = sizes[:k].cpu().numpy()
+    exp = D.stats(s_np, 1, r_max, n_bins)
+    assert hist.cpu().tolist() == exp[0].tolist() and c == [exp[1], exp[2]], "droplet statistics differ from the oracle"
+    assert hk.device_error() == 0
+    return out
+
+
 def calibration_copy(torch, nbytes=1 << 30):
     """One plain device copy of `nbytes` (read nbytes + write nbytes), for
     scaling the HBM byte counters of a counter run."""
@@ -376,6 +429,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-classify", action="store_true")
+    ap.add_argument("--no-droplets", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run one 1 GiB device copy (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "TAG"),
                     help="write profiles/traffic_<KERNEL>_<TAG>.json from two rocprofv3 --pmc runs and exit")
@@ -492,6 +546,10 @@ def main():
         torch.cuda.empty_cache()
         result["classify"] = bench_classify(hk, torch)
         log(f"classify: {result['classify']}")
+    if not args.no_droplets:
+        torch.cuda.empty_cache()
+        result["droplets"] = bench_droplets(hk, torch)
+        log(f"droplets: {result['droplets']}")
     if not args.no_cpu_baseline:
         planes = min(args.cpu_planes, edge)
         result["cpu_baseline"] = cpu_baseline(phi_np, mask, planes)

@@ -120,6 +120,29 @@ int hk_label_batched(const hk_job *jobs, int32_t n_jobs, hipStream_t stream);
 int hk_classify(const float *I, const int32_t *labels, int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask,
                 const int64_t *n_clusters, int64_t *neg, int64_t *pos, int8_t *inside, hipStream_t stream);
 
+/*
+ * hk_droplet_stats: Sec. 5 -- cluster sizes as the radius of the sphere of
+ * the same volume, R = (3 s / (4 pi))^(1/3) lattice units, over the clusters
+ * of at least min_size sites.
+ *   sizes         int64 [max_clusters], device, read only (hk_label output)
+ *   n_clusters    one int64, device: K (entries >= min(K, max_clusters) are
+ *                 not read)
+ *   r_max, n_bins histogram over [0, r_max) in n_bins (1..2048) bins of
+ *                 width w = r_max / n_bins; the last bin also takes R >= r_max
+ *   hist          int64 [n_bins], device, out: clusters per bin.  The bin is
+ *                 decided on the size: s >= (4 pi / 3) e^3 <=> R >= e, with
+ *                 the edge thresholds computed in IEEE double as
+ *                 c * (e * e * e), c = 4.0 * pi / 3.0, e = i * w -- exact.
+ *   counts        int64 [2], device, out: number of clusters counted, sum of
+ *                 their sizes
+ *   sums          double [3], device, out: sums of R, R^2, R^3 (summation
+ *                 order unspecified: these carry rounding)
+ * No host synchronisation; errors as for hk_label.
+ */
+int hk_droplet_stats(const int64_t *sizes, const int64_t *n_clusters, int64_t max_clusters, int64_t min_size,
+                     double r_max, int32_t n_bins, int64_t *hist, int64_t *counts, double *sums,
+                     hipStream_t stream);
+
 /* ceil(nx*ny*nz / 2): the Sec. 3 bound on the number of clusters, i.e. the
  * capacity `sizes` must have.  0 for invalid edges. */
 int64_t hk_max_clusters(int32_t nx, int32_t ny, int32_t nz);

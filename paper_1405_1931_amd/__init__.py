@@ -197,6 +197,29 @@ def classify(I, labels, n_clusters, periodic=0, stream=None):
     return neg[:k], pos[:k], inside[:k]
 
 
+def droplet_stats_into(sizes, n_clusters, min_size, r_max, n_bins, hist, counts, sums, stream=None):
+    """Enqueue the droplet-size statistics of `sizes` (no synchronisation)."""
+    rc = _lib.load().hk_droplet_stats(sizes.data_ptr(), n_clusters.data_ptr(), int(sizes.numel()), int(min_size),
+                                      float(r_max), int(n_bins), hist.data_ptr(), counts.data_ptr(),
+                                      sums.data_ptr(), _stream_handle(stream))
+    _lib.check(rc, "hk_droplet_stats")
+
+
+def droplet_stats(sizes, n_clusters, min_size=1, r_max=32.0, n_bins=64, stream=None):
+    """(hist, count, sum of sizes, sum R, sum R^2, sum R^3) of the clusters
+    with >= min_size sites, R the radius of the sphere of equal volume."""
+    import torch
+
+    dev = sizes.device
+    hist = torch.empty(n_bins, dtype=torch.int64, device=dev)
+    counts = torch.empty(2, dtype=torch.int64, device=dev)
+    sums = torch.empty(3, dtype=torch.float64, device=dev)
+    droplet_stats_into(sizes, n_clusters, min_size, r_max, n_bins, hist, counts, sums, stream=stream)
+    c = counts.tolist()
+    sm = sums.tolist()
+    return hist, c[0], c[1], sm[0], sm[1], sm[2]
+
+
 def autotune(phi, periodic=0, reps: int = 3, stream=None):
     """Time every candidate brick shape on this lattice and install the
     fastest for its size bucket; returns (by, bz, ms)."""

@@ -1,0 +1,78 @@
+"""GPU parity of the droplet-size statistics (Sec. 5): hk_droplet_stats against
+the oracle -- histogram, count and summed size exactly; the sums of R, R^2,
+R^3 within the rounding of K terms of about one ulp each, summed in any
+order (relative 4 K eps, eps = 2^-52, derived in the design doc)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import droplets as D
+from paper_1405_1931_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+EPS = 2.0 ** -52
+
+
+@pytest.fixture(scope="module")
+def hk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1405_1931_amd as hk
+
+    hk.set_brick(0, 0)
+    return hk
+
+
+def check(hk, sizes_np, min_size, r_max, n_bins, what):
+    print(f"[droplets] {what}: K={sizes_np.size} min {min_size} r_max {r_max} bins {n_bins}", flush=True)
+    sizes = torch.from_numpy(np.ascontiguousarray(sizes_np, dtype=np.int64)).cuda()
+    if sizes.numel() == 0:
+        sizes = torch.zeros(1, dtype=torch.int64, device="cuda")
+    k = torch.tensor([sizes_np.size], dtype=torch.int64, device="cuda")
+    got = hk.droplet_stats(sizes, k, min_size, r_max, n_bins)
+    exp = D.stats(sizes_np, min_size, r_max, n_bins)
+    assert np.array_equal(got[0].cpu().numpy(), exp[0]), what
+    assert got[1] == exp[1] and got[2] == exp[2], what
+    tol = 4.0 * max(1, sizes_np.size) * EPS
+    for g, e in zip(got[3:], exp[3:]):
+        assert abs(g - e) <= tol * max(1.0, abs(e)), (what, g, e)
+    return got
+
+
+def test_random_sizes(hk):
+    rng = np.random.default_rng(11)
+    sizes = np.concatenate([rng.integers(1, 40, 20000), rng.integers(40, 2_000_000, 3000), [4188, 4189, 1, 2]])
+    for min_size, r_max, n_bins in ((1, 32.0, 64), (3, 12.0, 7), (1, 100.0, 2048), (50, 5.0, 1)):
+        check(hk, sizes, min_size, r_max, n_bins, "random sizes")
+
+
+def test_empty_and_one(hk):
+    check(hk, np.zeros(0, dtype=np.int64), 1, 10.0, 8, "no clusters")
+    got = check(hk, np.array([1], dtype=np.int64), 1, 1.0, 4, "one site")
+    assert got[0].cpu().tolist() == [0, 0, 1, 0]
+
+
+def test_droplet_field_sizes(hk):
+    """Sizes of a labelled droplet field (config 2 at 1/4 and full size)."""
+    for scale in (4, 1):
+        phi_np, mask = W.config(2, scale)
+        phi = torch.from_numpy(phi_np).cuda()
+        labels, k, sizes = hk.label(phi, mask)
+        s = sizes.cpu().numpy()
+        check(hk, s, 1, 40.0, 80, f"droplets 1/{scale}")
+        check(hk, s, 27, 40.0, 80, f"droplets 1/{scale}, min 27")
+    assert hk.device_error() == 0
+
+
+def test_argument_errors(hk):
+    from paper_1405_1931_amd import _lib
+
+    sizes = torch.ones(4, dtype=torch.int64, device="cuda")
+    k = torch.tensor([4], dtype=torch.int64, device="cuda")
+    for r_max, n_bins in ((0.0, 4), (-1.0, 4), (float("inf"), 4), (1.0, 0), (1.0, 4096)):
+        with pytest.raises(_lib.HkError):
+            hk.droplet_stats(sizes, k, 1, r_max, n_bins)
