@@ -211,9 +211,10 @@ def bench_served(hk, torch, bufs, capacity_jobs_s, runs=4, slots=3, max_batch=64
 
 
 def bench_classify(hk, torch, reps=20):
-    """Config 4 (capsules 256x256x512, z periodic): hk_label on the sites that
-    kept I0, then the interior/exterior decision (Sec. 6).  Times the decision
-    alone (its three kernels, HIP events on the launch stream); algorithmic
+    """Config 4 (capsules 256x256x512, z periodic): hk_label_pred on the sites
+    that kept I0, then the interior/exterior decision (Sec. 6).  Times each
+    (HIP events on the launch stream); the roofline is the decision's (its
+    three kernels); algorithmic
     bytes = labels and I read once (8 B/site) + neg, pos, inside written
     (17 B/cluster)."""
     import numpy as np
@@ -232,21 +233,31 @@ def bench_classify(hk, torch, reps=20):
     neg = torch.empty(cap, dtype=torch.int64, device="cuda")
     pos = torch.empty(cap, dtype=torch.int64, device="cuda")
     inside = torch.empty(cap, dtype=torch.int8, device="cuda")
-    hk.label_into(phi, mask, labels, kbuf, sizes)
-    for _ in range(3):
+    # the HK pass of Sec. 6: the sites whose proximity value is still I0
+    def lab():
+        hk.label_pred_into(I, "eq", W.I0, mask, labels, kbuf, sizes)
+
+    def cls():
         hk.classify_into(I, labels, kbuf, mask, neg, pos, inside)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        hk.classify_into(I, labels, kbuf, mask, neg, pos, inside)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+
+    times = {}
+    for name, fn in (("label", lab), ("classify", cls)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        times[name] = e0.elapsed_time(e1) / reps
+    ms = times["classify"]
     k = int(kbuf.item())
     ins = inside[:k].cpu().numpy()
     alg = 8 * n + 17 * k
     out = {"workload": f"capsules {nx}x{ny}x{nz} mask {mask} ({k - 1} capsules)", "ms": round(ms, 4),
+           "label_eq_i0_ms": round(times["label"], 4),
            "gsites_per_s": round(n / ms / 1e6, 2), "clusters": k,
            "interiors": int((ins == 1).sum()), "exteriors": int((ins == 0).sum()), "undecided": int((ins == -1).sum()),
            "roofline": {"bound": "hbm", "algorithmic_bytes": alg, "achieved": round(alg / ms / 1e6, 1),

@@ -73,6 +73,31 @@ typedef enum {
 int hk_label(const float *phi, int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask,
              int32_t *labels, int64_t *n_clusters, int64_t *sizes, hipStream_t stream);
 
+/* Occupancy predicates of hk_label_pred. */
+typedef enum {
+    HK_PRED_GT = 0, /* float32 field: occupied iff field > param */
+    HK_PRED_EQ = 1, /* float32 field: occupied iff field == param */
+    HK_PRED_U8 = 2  /* uint8 field: occupied iff field != 0 (param unused) */
+} hk_predicate;
+
+/*
+ * hk_label_pred: hk_label with another occupancy condition.  Sec. 2 labels
+ * the sites where phi > 0; the interior detection of Sec. 6 labels the sites
+ * whose proximity value still equals the far-field value (HK_PRED_EQ with
+ * that value), and a caller may hold a threshold other than 0 or a ready
+ * byte mask.  Comparisons follow IEEE single precision and are decided on
+ * the bits (no flush-to-zero mode changes them): NaN sites are never
+ * occupied, +0 equals -0, denormals compare by value.
+ *   field        [nz][ny][nx] float32 (HK_PRED_GT, HK_PRED_EQ) or uint8
+ *                (HK_PRED_U8), device, read only
+ *   predicate    an hk_predicate value
+ *   param        the threshold or value; NaN is rejected for GT and EQ.
+ *                HK_PRED_GT with param +-0 is exactly hk_label.
+ * Other arguments, outputs, workspace and errors as in hk_label.
+ */
+int hk_label_pred(const void *field, int32_t predicate, float param, int32_t nx, int32_t ny, int32_t nz,
+                  uint32_t periodic_mask, int32_t *labels, int64_t *n_clusters, int64_t *sizes, hipStream_t stream);
+
 /* One lattice of a batch; fields as in hk_label. */
 typedef struct {
     const float *phi;

@@ -94,6 +94,41 @@ def label(phi, periodic=0, stream=None, sizes=True):
     return labels, kk, (sz[:kk] if sz is not None else None)
 
 
+_PREDICATES = {"gt": _lib.HK_PRED_GT, "eq": _lib.HK_PRED_EQ, "u8": _lib.HK_PRED_U8}
+
+
+def label_pred_into(field, predicate, param, mask, labels, n_clusters, sizes=None, stream=None):
+    """Enqueue the labelling of the sites where `predicate` holds: "gt"
+    (field > param), "eq" (field == param) on a float32 field, or "u8"
+    (field != 0) on a uint8 field; no synchronisation."""
+    import torch
+
+    pk = _PREDICATES[predicate]
+    want = torch.uint8 if pk == _lib.HK_PRED_U8 else torch.float32
+    if not isinstance(field, torch.Tensor) or field.dtype != want or not field.is_cuda:
+        raise TypeError(f"field must be a {want} tensor on the GPU for predicate {predicate!r}")
+    if field.dim() != 3 or not field.is_contiguous():
+        raise ValueError("field must be a contiguous (nz, ny, nx) tensor")
+    nz, ny, nx = field.shape
+    rc = _lib.load().hk_label_pred(
+        field.data_ptr(), pk, float(param), nx, ny, nz, mask_of(mask), labels.data_ptr(), n_clusters.data_ptr(),
+        sizes.data_ptr() if sizes is not None else None, _stream_handle(stream))
+    _lib.check(rc, "hk_label_pred")
+
+
+def label_pred(field, predicate, param=0.0, periodic=0, stream=None):
+    """label() for another occupancy predicate (see label_pred_into)."""
+    import torch
+
+    nz, ny, nx = field.shape
+    labels = torch.empty(field.shape, dtype=torch.int32, device=field.device)
+    k = torch.zeros(1, dtype=torch.int64, device=field.device)
+    sz = torch.empty(max(1, max_clusters(nx, ny, nz)), dtype=torch.int64, device=field.device)
+    label_pred_into(field, predicate, param, periodic, labels, k, sz, stream=stream)
+    kk = int(k.item())
+    return labels, kk, sz[:kk]
+
+
 def _jobs_array(jobs):
     arr = (_lib.HkJob * max(1, len(jobs)))()
     for i, j in enumerate(jobs):

@@ -20,6 +20,7 @@ HK_ERR_NO_WORKSPACE = -3
 HK_ERR_HIP = -4
 HK_ERR_DEVICE = -5
 HK_ERR_TIMEOUT = -6
+HK_PRED_GT, HK_PRED_EQ, HK_PRED_U8 = 0, 1, 2
 
 
 class HkJob(ctypes.Structure):
@@ -64,6 +65,7 @@ _I64 = ctypes.c_int64
 _SIGS = {
     "hk_label": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "hk_label_pred": (ctypes.c_int, [_P, _I32, ctypes.c_float, _I32, _I32, _I32, ctypes.c_uint32, _P, _P, _P, _P]),
     "hk_label_batched": (ctypes.c_int, [ctypes.POINTER(HkJob), ctypes.c_int32, ctypes.c_void_p]),
     "hk_max_clusters": (ctypes.c_int64, [ctypes.c_int32] * 3),
     "hk_workspace_bytes": (ctypes.c_int64, [ctypes.c_int32] * 3),

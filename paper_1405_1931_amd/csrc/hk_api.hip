@@ -319,12 +319,17 @@ int64_t hk_workspace_bytes(int32_t nx, int32_t ny, int32_t nz) {
     return layout_of(g, 0).total + kErrBytes;
 }
 
-int hk_label(const float *phi, int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask, int32_t *labels,
-             int64_t *n_clusters, int64_t *sizes, hipStream_t stream) {
-    if (!phi || !labels || !n_clusters) return HK_ERR_INVALID_ARG;
+}  // extern "C"
+
+namespace {
+
+// hk_label and hk_label_pred: one lattice, the field read by predicate pk
+int label_one(const void *field, int pk, int32_t tkey, int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask,
+              int32_t *labels, int64_t *n_clusters, int64_t *sizes, hipStream_t stream) {
+    if (!field || !labels || !n_clusters) return HK_ERR_INVALID_ARG;
     int rc = check_shape(nx, ny, nz, periodic_mask);
     if (rc != HK_OK) return rc;
-    if ((const void *)labels == (const void *)phi) return HK_ERR_INVALID_ARG;
+    if ((const void *)labels == field) return HK_ERR_INVALID_ARG;
     Geo g;
     rc = plan_lattice(nx, ny, nz, periodic_mask, &g);
     if (rc != HK_OK) return rc;
@@ -335,14 +340,46 @@ int hk_label(const float *phi, int32_t nx, int32_t ny, int32_t nz, uint32_t peri
     if (rc != HK_OK) return rc;
     g.err = (int32_t *)ws->base;
     bind(&g, ws->base + kErrBytes, L);
-    g.phi = phi;
+    g.phi = (const float *)field;
+    g.tkey = tkey;
     g.labels = labels;
     g.n_clusters = n_clusters;
     g.sizes = sizes;
     (void)hipGetLastError();
     hipEvent_t *ev = profile_events();
-    if (launch_single(g, stream, ev) != hipSuccess) return HK_ERR_HIP;
+    if (launch_single(g, stream, ev, pk) != hipSuccess) return HK_ERR_HIP;
     return HK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hk_label(const float *phi, int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask, int32_t *labels,
+             int64_t *n_clusters, int64_t *sizes, hipStream_t stream) {
+    return label_one(phi, PK_GT0, 0, nx, ny, nz, periodic_mask, labels, n_clusters, sizes, stream);
+}
+
+int hk_label_pred(const void *field, int32_t predicate, float param, int32_t nx, int32_t ny, int32_t nz,
+                  uint32_t periodic_mask, int32_t *labels, int64_t *n_clusters, int64_t *sizes, hipStream_t stream) {
+    uint32_t pb;
+    std::memcpy(&pb, &param, sizeof pb);
+    const bool nan = (pb & 0x7fffffffu) > 0x7f800000u;
+    int pk;
+    switch (predicate) {
+        case HK_PRED_GT:
+            if (nan) return HK_ERR_INVALID_ARG;
+            // field > +-0 is the cluster condition itself: share its kernel
+            pk = order_key(pb) == 0 ? PK_GT0 : PK_GT;
+            break;
+        case HK_PRED_EQ:
+            if (nan) return HK_ERR_INVALID_ARG;
+            pk = PK_EQ;
+            break;
+        case HK_PRED_U8: pk = PK_U8; break;
+        default: return HK_ERR_INVALID_ARG;
+    }
+    return label_one(field, pk, order_key(pb), nx, ny, nz, periodic_mask, labels, n_clusters, sizes, stream);
 }
 
 int hk_reserve(int64_t bytes, hipStream_t stream) {

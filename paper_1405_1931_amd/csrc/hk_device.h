@@ -63,7 +63,8 @@ struct Geo {
     int32_t rows;     // ny * nz lattice rows
     int32_t nblk;     // ceil(rows / WG)
     // caller buffers
-    const float *phi;
+    const float *phi;  // the field (float32, or uint8 for PK_U8)
+    int32_t tkey;      // order key of the predicate's threshold / value
     int32_t *labels;
     int64_t *n_clusters;
     int64_t *sizes;
@@ -116,11 +117,42 @@ struct __align__(16) LdsBrick {
 
 __device__ __forceinline__ void set_err(const Geo &g, int code) { atomicOr(g.err, code); }
 
-// phi > 0 in IEEE single precision, decided on the bit pattern so that no
-// flush-to-zero mode can change it: positive finite or +inf, not NaN, not +0.
-__device__ __forceinline__ bool occupied(float v) {
-    const int b = __float_as_int(v);
-    return b > 0 && b <= 0x7f800000;
+// Occupancy predicates.  PK_GT0 is the cluster condition phi > 0 of Sec. 2;
+// the others let a caller label another set of sites (the capsule algorithm
+// of Sec. 6 labels the sites whose proximity value equals the far-field
+// value).  Values are the hk_predicate codes; PK_GT0 is internal.
+constexpr int PK_GT = 0;   // float32 field > t
+constexpr int PK_EQ = 1;   // float32 field == t
+constexpr int PK_U8 = 2;   // uint8 field != 0
+constexpr int PK_GT0 = 3;  // float32 field > 0
+
+// An integer key that orders float bit patterns as IEEE orders the values:
+// -|b| for negative values, b otherwise, so +0 and -0 share key 0 and
+// denormals keep their place.  NaN patterns are excluded by the callers.
+__host__ __device__ __forceinline__ int32_t order_key(uint32_t b) {
+    return (b >> 31) ? -(int32_t)(b & 0x7fffffffu) : (int32_t)b;
+}
+
+// The predicate on a raw 32-bit load (float bits, or a zero-extended byte),
+// decided on the bits so that no flush-to-zero mode can change it.
+template <int PK>
+__device__ __forceinline__ bool occupied_raw(uint32_t b, int32_t tkey) {
+    if constexpr (PK == PK_GT0) {
+        // positive finite or +inf: not NaN, not +-0, not negative
+        return (int32_t)b > 0 && (int32_t)b <= 0x7f800000;
+    } else if constexpr (PK == PK_U8) {
+        return b != 0u;
+    } else {
+        const bool num = (b & 0x7fffffffu) <= 0x7f800000u;  // not NaN
+        if constexpr (PK == PK_GT) return num && order_key(b) > tkey;
+        else return num && order_key(b) == tkey;
+    }
+}
+
+// a raw value that no predicate accepts (a NaN pattern, or a zero byte)
+template <int PK>
+__device__ __forceinline__ constexpr uint32_t raw_empty() {
+    return PK == PK_U8 ? 0u : 0x7fc00000u;
 }
 
 __device__ __forceinline__ uint64_t run_starts(uint64_t w) { return w & ~(w << 1); }
@@ -386,26 +418,34 @@ __device__ __forceinline__ void wave_band(const Geo &g, int *r0, int *r1) {
     *r1 = min(g.R, *r0 + rpw);
 }
 
-// lane x loads site x of rows base .. base+OCC_U-1 (0 outside the lattice)
-__device__ __forceinline__ void fetch_rows(const Geo &g, const Brick &k, int base, int r1, float (&v)[OCC_U]) {
+// lane x loads site x of rows base .. base+OCC_U-1 as raw bits (a value no
+// predicate accepts outside the lattice)
+template <int PK>
+__device__ __forceinline__ void fetch_rows(const Geo &g, const Brick &k, int base, int r1, uint32_t (&v)[OCC_U]) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int j = 0; j < OCC_U; ++j) {
         const int r = base + j;
         const int yl = r & (g.BY - 1), zl = r >> g.lby;
-        v[j] = 0.0f;
-        if (r < r1 && yl < k.ey && zl < k.ez && lane < k.ex)
-            v[j] = g.phi[((int64_t)(k.z0 + zl) * g.ny + (k.y0 + yl)) * g.nx + k.x0 + lane];
+        v[j] = raw_empty<PK>();
+        if (r < r1 && yl < k.ey && zl < k.ez && lane < k.ex) {
+            const int64_t i = ((int64_t)(k.z0 + zl) * g.ny + (k.y0 + yl)) * g.nx + k.x0 + lane;
+            if constexpr (PK == PK_U8)
+                v[j] = reinterpret_cast<const uint8_t *>(g.phi)[i];
+            else
+                v[j] = __float_as_uint(g.phi[i]);
+        }
     }
 }
 
 // one ballot per row: the row's occupancy word, to LDS and to the brick's words
-__device__ __forceinline__ void ballot_rows(const Geo &g, int b, int base, int r1, const float (&v)[OCC_U],
+template <int PK>
+__device__ __forceinline__ void ballot_rows(const Geo &g, int b, int base, int r1, const uint32_t (&v)[OCC_U],
                                             LdsBrick &s) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
     for (int j = 0; j < OCC_U; ++j) {
-        const uint64_t m = __ballot(occupied(v[j]));
+        const uint64_t m = __ballot(occupied_raw<PK>(v[j], g.tkey));
         if (lane == 0 && base + j < r1) {
             s.occ[base + j] = m;
             g.occ[(int64_t)b * g.R + base + j] = m;
@@ -414,13 +454,14 @@ __device__ __forceinline__ void ballot_rows(const Geo &g, int b, int base, int r
 }
 
 // occupancy of a brick, OCC_U rows in flight per wave
+template <int PK>
 __device__ __forceinline__ void load_occupancy(const Geo &g, const Brick &k, int b, LdsBrick &s) {
     int r0, r1;
     wave_band(g, &r0, &r1);
     for (int base = r0; base < r1; base += OCC_U) {
-        float v[OCC_U];
-        fetch_rows(g, k, base, r1, v);
-        ballot_rows(g, b, base, r1, v, s);
+        uint32_t v[OCC_U];
+        fetch_rows<PK>(g, k, base, r1, v);
+        ballot_rows<PK>(g, b, base, r1, v, s);
     }
 }
 
@@ -737,9 +778,10 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
     }
 }
 
+template <int PK = PK_GT0>
 __device__ __forceinline__ void phase_local(const Geo &g, int b, LdsBrick &s) {
     const Brick k = brick_of(g, b);
-    load_occupancy(g, k, b, s);
+    load_occupancy<PK>(g, k, b, s);
     local_labels(g, k, b, s);
 }
 

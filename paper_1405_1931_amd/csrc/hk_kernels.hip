@@ -5,9 +5,10 @@
 
 namespace hk {
 
+template <int PK>
 __global__ __launch_bounds__(WG) void k_local(Geo g) {
     __shared__ LdsBrick s;
-    phase_local(g, blockIdx.x, s);
+    phase_local<PK>(g, blockIdx.x, s);
 }
 
 __global__ __launch_bounds__(WG_NODES) void k_merge(Geo g) {
@@ -47,13 +48,18 @@ __global__ __launch_bounds__(WG) void k_write(Geo g) {
 const char *const kPhaseNames[kPhases] = {"k_local",  "k_merge",  "k_roots", "k_rowsum",
                                           "k_scanblk", "k_rowpre", "k_canon", "k_write"};
 
-hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev) {
+hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev, int pk) {
     const dim3 blk(WG), small(WG_NODES);
     auto mark = [&](int i) {
         if (ev) (void)hipEventRecord(ev[i], st);
     };
     mark(0);
-    hipLaunchKernelGGL(k_local, dim3(g.nb), blk, 0, st, g);
+    switch (pk) {
+        case PK_GT: hipLaunchKernelGGL(k_local<PK_GT>, dim3(g.nb), blk, 0, st, g); break;
+        case PK_EQ: hipLaunchKernelGGL(k_local<PK_EQ>, dim3(g.nb), blk, 0, st, g); break;
+        case PK_U8: hipLaunchKernelGGL(k_local<PK_U8>, dim3(g.nb), blk, 0, st, g); break;
+        default: hipLaunchKernelGGL(k_local<PK_GT0>, dim3(g.nb), blk, 0, st, g); break;
+    }
     mark(1);
     hipLaunchKernelGGL(k_merge, dim3(g.nb), small, 0, st, g);
     mark(2);

@@ -11,7 +11,8 @@ constexpr int kPhases = 8;
 extern const char *const kPhaseNames[kPhases];
 
 // enqueue the eight single-lattice phases on `st`; when `ev` is non-null,
-// ev[0..kPhases] are recorded on `st` before each kernel and after the last
-hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev);
+// ev[0..kPhases] are recorded on `st` before each kernel and after the last;
+// `pk` selects the occupancy predicate (PK_*) of the brick phase
+hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev, int pk = PK_GT0);
 
 }  // namespace hk

@@ -132,3 +132,21 @@ def test_autotune_argument_errors_without_gpu(lib):
     assert lib.hk_autotune(dummy, 4, 4, 4, 0, dummy, dummy, None, 0, None, *args) == _lib.HK_ERR_INVALID_ARG
     assert lib.hk_autotune_batched(None, 2, 3, None, *args) == _lib.HK_ERR_INVALID_ARG
     assert lib.hk_autotune_batched(None, 0, 3, None, *args) == _lib.HK_ERR_INVALID_ARG
+
+
+def test_label_pred_argument_errors_without_gpu(lib):
+    dummy = ctypes.c_void_p(0x1000)
+    other = ctypes.c_void_p(0x2000)
+    nan = float("nan")
+    # unknown predicate, NaN threshold or value: rejected before any GPU call
+    assert lib.hk_label_pred(dummy, 3, 0.0, 4, 4, 4, 0, other, other, None, None) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_label_pred(dummy, -1, 0.0, 4, 4, 4, 0, other, other, None, None) == _lib.HK_ERR_INVALID_ARG
+    for pred in (_lib.HK_PRED_GT, _lib.HK_PRED_EQ):
+        assert lib.hk_label_pred(dummy, pred, nan, 4, 4, 4, 0, other, other, None, None) == _lib.HK_ERR_INVALID_ARG
+    # null pointers, bad shapes, labels aliasing the field
+    assert lib.hk_label_pred(None, 0, 0.0, 4, 4, 4, 0, other, other, None, None) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_label_pred(dummy, 2, 0.0, 4, 4, 4, 0, None, other, None, None) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_label_pred(dummy, 1, 0.0, 0, 4, 4, 0, other, other, None, None) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_label_pred(dummy, 1, 0.0, 4, 4, 4, 8, other, other, None, None) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_label_pred(dummy, 0, 0.5, 4, 4, 4, 0, dummy, other, None, None) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_label_pred(dummy, 0, 0.5, 2048, 2048, 1024, 0, other, other, None, None) == _lib.HK_ERR_TOO_LARGE
