@@ -28,7 +28,8 @@
 
 namespace hk {
 
-__global__ __launch_bounds__(WG) void kb_local(GroupView v) {
+// eight waves per SIMD, four bricks per CU, as for the single-lattice kernel
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8))) void kb_local(GroupView v) {
     __shared__ LdsBrick s;
     int i;
     const Geo &g = locate(v, 0, blockIdx.x, &i);

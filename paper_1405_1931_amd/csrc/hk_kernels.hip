@@ -5,8 +5,11 @@
 
 namespace hk {
 
+// Four bricks per CU need eight waves per SIMD: the LDS allows four (40 KB
+// each), and the compiler is held to the scalar registers of eight waves (it
+// would otherwise use 106, room for seven waves and three bricks).
 template <int PK>
-__global__ __launch_bounds__(WG) void k_local(Geo g) {
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8))) void k_local(Geo g) {
     __shared__ LdsBrick s;
     phase_local<PK>(g, blockIdx.x, s);
 }
