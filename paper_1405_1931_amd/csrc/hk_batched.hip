@@ -36,7 +36,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8))) void kb
     phase_local(g, i, s);
 }
 
-__global__ __launch_bounds__(WG_NODES) void kb_merge(GroupView v) {
+__global__ __launch_bounds__(WG_NODES) __attribute__((amdgpu_waves_per_eu(8))) void kb_merge(GroupView v) {
     __shared__ MergeLds m;
     int i;
     const Geo &g = locate(v, 1, blockIdx.x, &i);

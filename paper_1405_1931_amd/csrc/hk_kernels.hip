@@ -16,7 +16,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8))) void k_
     phase_local<PK>(g, blockIdx.x, s);
 }
 
-__global__ __launch_bounds__(WG_NODES) void k_merge(Geo g) {
+__global__ __launch_bounds__(WG_NODES) __attribute__((amdgpu_waves_per_eu(8))) void k_merge(Geo g) {
     __shared__ MergeLds m;
     phase_merge(g, blockIdx.x, m);
 }
