@@ -573,10 +573,12 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
     }
     __syncthreads();
     const int ne = s.tmp[20];
-    jump_flatten(s, total);
 
-    // equivalences: union of the (now flat) trees, linking toward the
-    // smaller run, so each component's root is its first run
+    // equivalences: union of the trees, linking toward the smaller run, so
+    // each component's root is its first run.  Every parent is an earlier
+    // run, so the finds of the unions walk the unflattened trees as they
+    // are (halving them); one flatten at the end costs less than one here
+    // and another after.
     const int stored = min(ne, MAXRUNS - total);
     for (int e = t; e < stored; e += WG) {
         const int v = s.par[total + e];
