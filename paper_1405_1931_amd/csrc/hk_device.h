@@ -429,7 +429,10 @@ __device__ __forceinline__ void fetch_rows(const Geo &g, const Brick &k, int bas
         const int yl = r & (g.BY - 1), zl = r >> g.lby;
         v[j] = raw_empty<PK>();
         if (r < r1 && yl < k.ey && zl < k.ez && lane < k.ex) {
-            const int64_t i = ((int64_t)(k.z0 + zl) * g.ny + (k.y0 + yl)) * g.nx + k.x0 + lane;
+            // every partial product is a site index below N <= 2^31 - 1, so
+            // 32-bit arithmetic is exact (and costs a few scalar operations
+            // per row instead of 64-bit multiplies)
+            const uint32_t i = (uint32_t)(((k.z0 + zl) * g.ny + (k.y0 + yl)) * g.nx + k.x0) + (uint32_t)lane;
             if constexpr (PK == PK_U8)
                 v[j] = reinterpret_cast<const uint8_t *>(g.phi)[i];
             else
@@ -443,12 +446,13 @@ template <int PK>
 __device__ __forceinline__ void ballot_rows(const Geo &g, int b, int base, int r1, const uint32_t (&v)[OCC_U],
                                             LdsBrick &s) {
     const int lane = threadIdx.x & 63;
+    uint64_t *occb = g.occ + (int64_t)b * g.R;
 #pragma unroll
     for (int j = 0; j < OCC_U; ++j) {
         const uint64_t m = __ballot(occupied_raw<PK>(v[j], g.tkey));
         if (lane == 0 && base + j < r1) {
             s.occ[base + j] = m;
-            g.occ[(int64_t)b * g.R + base + j] = m;
+            occb[base + j] = m;
         }
     }
 }
