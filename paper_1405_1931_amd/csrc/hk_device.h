@@ -419,41 +419,54 @@ __device__ __forceinline__ void wave_band(const Geo &g, int *r0, int *r1) {
 }
 
 // lane x loads site x of rows base .. base+OCC_U-1 as raw bits (a value no
-// predicate accepts outside the lattice)
+// predicate accepts outside the lattice).  Every partial product of an index
+// is a site index below N <= 2^31 - 1, so 32-bit arithmetic is exact.  A
+// batch of rows that lies wholly inside a full brick (the common case) needs
+// no bounds checks and no lane masks; the others check each row and lane.
+template <int PK>
+__device__ __forceinline__ uint32_t load_raw(const Geo &g, uint32_t i) {
+    if constexpr (PK == PK_U8)
+        return reinterpret_cast<const uint8_t *>(g.phi)[i];
+    else
+        return __float_as_uint(g.phi[i]);
+}
+
 template <int PK>
 __device__ __forceinline__ void fetch_rows(const Geo &g, const Brick &k, int base, int r1, uint32_t (&v)[OCC_U]) {
     const int lane = threadIdx.x & 63;
+    const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny;
+    const bool full = k.ex == 64 && k.ey == g.BY && k.ez == g.BZ && base + OCC_U <= r1;
+    if (full) {
+#pragma unroll
+        for (int j = 0; j < OCC_U; ++j) {
+            const int r = base + j;
+            const int yl = r & (g.BY - 1), zl = r >> g.lby;
+            const uint32_t ri = ((uint32_t)(k.z0 + zl) * ny + (uint32_t)(k.y0 + yl)) * nx + (uint32_t)k.x0;
+            v[j] = load_raw<PK>(g, ri + (uint32_t)lane);
+        }
+        return;
+    }
 #pragma unroll
     for (int j = 0; j < OCC_U; ++j) {
         const int r = base + j;
         const int yl = r & (g.BY - 1), zl = r >> g.lby;
         v[j] = raw_empty<PK>();
         if (r < r1 && yl < k.ey && zl < k.ez && lane < k.ex) {
-            // every partial product is a site index below N <= 2^31 - 1, so
-            // 32-bit arithmetic is exact (and costs a few scalar operations
-            // per row instead of 64-bit multiplies)
-            const uint32_t i = (uint32_t)(((k.z0 + zl) * g.ny + (k.y0 + yl)) * g.nx + k.x0) + (uint32_t)lane;
-            if constexpr (PK == PK_U8)
-                v[j] = reinterpret_cast<const uint8_t *>(g.phi)[i];
-            else
-                v[j] = __float_as_uint(g.phi[i]);
+            const uint32_t ri = ((uint32_t)(k.z0 + zl) * ny + (uint32_t)(k.y0 + yl)) * nx + (uint32_t)k.x0;
+            v[j] = load_raw<PK>(g, ri + (uint32_t)lane);
         }
     }
 }
 
-// one ballot per row: the row's occupancy word, to LDS and to the brick's words
+// one ballot per row: the row's occupancy word, to LDS (the brick's words
+// are copied out to HBM once the whole brick is in)
 template <int PK>
-__device__ __forceinline__ void ballot_rows(const Geo &g, int b, int base, int r1, const uint32_t (&v)[OCC_U],
-                                            LdsBrick &s) {
+__device__ __forceinline__ void ballot_rows(const Geo &g, int base, int r1, const uint32_t (&v)[OCC_U], LdsBrick &s) {
     const int lane = threadIdx.x & 63;
-    uint64_t *occb = g.occ + (int64_t)b * g.R;
 #pragma unroll
     for (int j = 0; j < OCC_U; ++j) {
         const uint64_t m = __ballot(occupied_raw<PK>(v[j], g.tkey));
-        if (lane == 0 && base + j < r1) {
-            s.occ[base + j] = m;
-            occb[base + j] = m;
-        }
+        if (lane == 0 && base + j < r1) s.occ[base + j] = m;
     }
 }
 
@@ -465,7 +478,7 @@ __device__ __forceinline__ void load_occupancy(const Geo &g, const Brick &k, int
     for (int base = r0; base < r1; base += OCC_U) {
         uint32_t v[OCC_U];
         fetch_rows<PK>(g, k, base, r1, v);
-        ballot_rows<PK>(g, b, base, r1, v, s);
+        ballot_rows<PK>(g, base, r1, v, s);
     }
 }
 
@@ -672,6 +685,7 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
     const int R = g.R;
     if (t < R) s.rootw[t] = 0ull;
     __syncthreads();
+    if (t < R) g.occ[(int64_t)b * R + t] = s.occ[t];  // the words, for the later phases
     const CoreOut co = brick_core(g, k, s);
 
     // component slots: boundary components take 0..B-1 (their node slots),
