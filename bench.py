@@ -338,6 +338,62 @@ def calibration_copy(torch, nbytes=1 << 30):
     del a, b
 
 
+TRACE_CMD = ("cd /tmp && TMPDIR=/tmp rocprofv3 --kernel-trace --stats -d /root/repo/gpurun_out/prof -o run -- "
+             "python3 /root/repo/bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-batched --no-served")
+
+
+def _kernel_name(full):
+    """Short kernel name: namespace and template arguments kept, parameters dropped."""
+    n = full.replace("(anonymous namespace)::", "")
+    if n.startswith("void "):
+        n = n[5:]
+    return n.split("(")[0]
+
+
+def summarize_trace(db):
+    """Split the kernel trace of TRACE_CMD (a rocprofv3 database) into its
+    sections -- the 1024^3 labelling steps, the capsule decision, the droplet
+    statistics -- by dispatch order, and write one per-kernel summary per
+    section to profiles/."""
+    import sqlite3
+
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, start, end, grid_x, workgroup_x from kernels order by start").fetchall()
+    ks = [(_kernel_name(n), s, e, gx, wx) for n, s, e, gx, wx in rows if "hk::" in n]
+    first = lambda pred: next(i for i, k in enumerate(ks) if pred(k[0]))
+    last = lambda pred: max(i for i, k in enumerate(ks) if pred(k[0]))
+    i_cls0 = first(lambda n: "k_local<1>" in n)          # the I == I0 labelling opens the decision
+    i_cls1 = last(lambda n: "k_cls_decide" in n)
+    i_ds1 = last(lambda n: "k_ds_stats" in n)
+    sections = [
+        ("kernel_trace_hk_label_percolation1024.txt",
+         "hk_label kernel trace, site percolation 1024^3 p=0.3116 periodic xyz, brick 64x16x16", ks[:i_cls0]),
+        ("kernel_trace_hk_classify_capsules512.txt",
+         "hk_label_pred (I == I0) and hk_classify kernel trace, capsules 256x256x512, 300 capsules, z periodic",
+         ks[i_cls0:i_cls1 + 1]),
+        ("kernel_trace_hk_droplet_stats_droplets512.txt",
+         "hk_label and hk_droplet_stats kernel trace, droplets 512^3 periodic xyz (r_max 40, 80 bins)",
+         ks[i_cls1 + 1:i_ds1 + 1]),
+    ]
+    for fname, title, part in sections:
+        agg = {}
+        for n, s, e, gx, wx in part:
+            a = agg.setdefault((n, gx // wx), [])
+            a.append((e - s) / 1e3)
+        tot = sum(sum(v) for v in agg.values())
+        lines = [f"# {title}", "", "command (on the MI355X box; the trace is split into the bench's sections by",
+                 "dispatch order with `python bench.py --summarize-trace <run_results.db>`):", "",
+                 f"    {TRACE_CMD}", "",
+                 f"{'kernel':<44} {'groups':>8} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}"]
+        for (n, groups), v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+            lines.append(f"{n[:44]:<44} {groups:>8} {len(v):>6} {sum(v) / len(v):>10.1f} {min(v):>10.1f} "
+                         f"{max(v):>10.1f} {100 * sum(v) / tot:>6.1f}")
+        path = os.path.join(ROOT, "profiles", fname)
+        with open(path, "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+        print(f"wrote {path}")
+
+
 def summarize_pmc(fetch_dir, write_dir, kernel, tag, calib_bytes=1 << 30):
     """Per-launch HBM bytes of `kernel` from two rocprofv3 --pmc runs (CSV
     output; FETCH_SIZE then WRITE_SIZE, KiB per dispatch), each scaled by the
@@ -360,7 +416,7 @@ def summarize_pmc(fetch_dir, write_dir, kernel, tag, calib_bytes=1 << 30):
     total = 0.0
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         vals = per_kernel(d, counter)
-        mine = [v for name, vs in vals.items() if name.split("(")[0].endswith(kernel) for v in vs]
+        mine = [v for name, vs in vals.items() if _kernel_name(name).split("<")[0].endswith(kernel) for v in vs]
         copy = [v for name, vs in vals.items() if "copy" in name.lower() or "elementwise" in name.lower() for v in vs]
         if not mine or not copy:
             raise SystemExit(f"{counter}: kernel {kernel} or calibration copy not found in {d}")
@@ -392,7 +448,7 @@ def traffic_table(fetch_dir, write_dir, tag, calib_bytes):
                     if r["Counter_Name"] != counter:
                         continue
                     e = rows.setdefault((counter, int(r["Dispatch_Id"])), {})
-                    e["name"] = r["Kernel_Name"].split("(")[0]
+                    e["name"] = _kernel_name(r["Kernel_Name"])
                     e["bytes"] = float(r["Counter_Value"]) * 1024.0
                     e["us"] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
     fac = {}
@@ -409,9 +465,9 @@ def traffic_table(fetch_dir, write_dir, tag, calib_bytes):
     lines = [f"# HBM traffic per kernel, hk_label, workload {tag}", "",
              "commands (from /tmp with TMPDIR=/tmp on the MI355X box; one counter per run):", "",
              f"    rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fetch_dir} -o run -- python3 bench.py "
-             "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-profile --calib-copy",
+             "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-served --no-classify --no-droplets --no-profile --calib-copy",
              f"    rocprofv3 --pmc WRITE_SIZE --output-format csv -d {write_dir} -o run -- python3 bench.py "
-             "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-profile --calib-copy",
+             "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-served --no-classify --no-droplets --no-profile --calib-copy",
              f"    python bench.py --summarize-pmc {fetch_dir} {write_dir} <kernel> {tag}", "",
              f"calibration: a {calib_bytes / 2**30:.0f} GiB device copy reads FETCH_SIZE "
              f"{1 / fac['FETCH_SIZE']:.4f}x and WRITE_SIZE {1 / fac['WRITE_SIZE']:.4f}x its size; the counts below are "
@@ -434,7 +490,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--edge", type=int, default=1024, help="lattice edge (default: the 1024^3 workload)")
-    ap.add_argument("--cpu-planes", type=int, default=384, help="z-planes of the oracle sample")
+    ap.add_argument("--cpu-planes", type=int, default=1024, help="z-planes of the oracle sample (default: the whole lattice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
@@ -442,9 +498,14 @@ def main():
     ap.add_argument("--no-classify", action="store_true")
     ap.add_argument("--no-droplets", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run one 1 GiB device copy (counter calibration)")
+    ap.add_argument("--summarize-trace", metavar="DB",
+                    help="write the per-section kernel summaries to profiles/ from a rocprofv3 trace database and exit")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "KERNEL", "TAG"),
                     help="write profiles/traffic_<KERNEL>_<TAG>.json from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
+        return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
         return
