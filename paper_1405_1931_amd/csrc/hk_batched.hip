@@ -45,9 +45,10 @@ __global__ __launch_bounds__(WG_NODES) __attribute__((amdgpu_waves_per_eu(8))) v
 
 __global__ __launch_bounds__(WG_NODES) void kb_roots(GroupView v) {
     __shared__ int32_t hash[2 * HT];
+    __shared__ uint64_t rbits[RMAX];
     int i;
     const Geo &g = locate(v, 2, blockIdx.x, &i);
-    phase_roots(g, i, 1, hash);
+    phase_roots(g, i, 1, hash, rbits);
 }
 
 __global__ __launch_bounds__(WG) void kb_rowsum(GroupView v) {

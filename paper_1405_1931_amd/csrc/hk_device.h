@@ -932,13 +932,22 @@ static_assert(2 * HT <= MAXRUNS, "the hash must fit in the run array of LdsBrick
 
 // Bricks b0 .. b0 + nbr - 1 share the LDS hash, so a root that many bricks
 // reach (the spanning cluster's) receives one global add per group of bricks.
-__device__ __forceinline__ void phase_roots(const Geo &g, int b0, int nbr, int32_t *hash) {
+constexpr int ROOTS_MAX = 4;  // bricks one roots workgroup may take
+
+// rbits: LDS words of the workgroup's bricks (ROOTS_MAX * RMAX).  A root node
+// sets its root bit in its own brick's words, and only the workgroup that
+// takes a brick touches that brick's words in this phase, so the bits are
+// gathered in LDS and merged into the words with plain loads and stores
+// instead of one device-scope atomic per root.
+__device__ __forceinline__ void phase_roots(const Geo &g, int b0, int nbr, int32_t *hash, uint64_t *rbits) {
     int32_t *hkey = hash, *hval = hash + HT;
     const int nt = blockDim.x;
     for (int i = threadIdx.x; i < HT; i += nt) {
         hkey[i] = -1;
         hval[i] = 0;
     }
+    const int nw = min(nbr, g.nb - b0) * g.R;  // words of the workgroup's bricks
+    for (int i = threadIdx.x; i < nw; i += nt) rbits[i] = 0ull;
     __syncthreads();
     for (int b = b0; b < b0 + nbr && b < g.nb; ++b) {
         const int cnt = g.bcount[b];
@@ -958,7 +967,7 @@ __device__ __forceinline__ void phase_roots(const Geo &g, int b0, int nbr, int32
                 g.nrootpos[n] = (((int64_t)(r / g.cap) * g.R + min(lr >> 6, g.R - 1)) << 6) | (lr & 63);
                 if (r == n) {
                     if ((lr >> 6) < g.R)
-                        atomicOr((unsigned long long *)(g.root + (int64_t)b * g.R + (lr >> 6)), 1ull << (lr & 63));
+                        atomicOr((unsigned long long *)(rbits + (b - b0) * g.R + (lr >> 6)), 1ull << (lr & 63));
                     else
                         set_err(g, ERR_RANGE);
                 } else {
@@ -983,6 +992,11 @@ __device__ __forceinline__ void phase_roots(const Geo &g, int b0, int nbr, int32
     for (int i = threadIdx.x; i < HT; i += nt) {
         const int r = hkey[i];
         if (r >= 0) atomicAdd(g.nsize + r, hval[i]);
+    }
+    uint64_t *gw = g.root + (int64_t)b0 * g.R;
+    for (int i = threadIdx.x; i < nw; i += nt) {
+        const uint64_t m = rbits[i];
+        if (m) gw[i] |= m;
     }
 }
 

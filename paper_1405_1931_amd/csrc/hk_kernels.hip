@@ -21,11 +21,12 @@ __global__ __launch_bounds__(WG_NODES) __attribute__((amdgpu_waves_per_eu(8))) v
     phase_merge(g, blockIdx.x, m);
 }
 
-constexpr int ROOTS_BRICKS = 4;  // bricks per workgroup of the roots phase
+constexpr int ROOTS_BRICKS = ROOTS_MAX;  // bricks per workgroup of the roots phase
 
 __global__ __launch_bounds__(WG_NODES) void k_roots(Geo g) {
     __shared__ int32_t hash[2 * HT];
-    phase_roots(g, blockIdx.x * ROOTS_BRICKS, ROOTS_BRICKS, hash);
+    __shared__ uint64_t rbits[ROOTS_MAX * RMAX];
+    phase_roots(g, blockIdx.x * ROOTS_BRICKS, ROOTS_BRICKS, hash, rbits);
 }
 
 __global__ __launch_bounds__(WG) void k_rowsum(Geo g) {
