@@ -112,7 +112,7 @@ typedef struct {
  * hk_label_batched: label n_jobs independent lattices of any shapes with one
  * launch per phase on `stream`, each covering the bricks of every job (the
  * job table itself is a HOST array; it is copied to the device by the call,
- * from pinned memory, so a captured call is one copy node and eight kernel
+ * from pinned memory, so a captured call is one copy node and seven kernel
  * nodes).  Each job's output is
  * identical to what hk_label gives for it alone.  Every job is validated
  * before anything is enqueued.  n_jobs == 0 is a no-op.

@@ -80,7 +80,7 @@ void choose_brick(int nx, int ny, int nz, bool batch, int *by, int *bz) {
 // ---------------------------------------------------------------- plans
 
 struct Layout {
-    int64_t occ, root, wpre, face, bcount, npar, nkey, nsize, nlpos, nrootpos, runlab, icomp, icount, ncanon, nrun,
+    int64_t occ, root, wpre, face, bcount, npar, nkey, nsize, nlpos, nrootpos, runlab, icomp, icount, nrun,
         rowcnt, blksum, total;
 };
 
@@ -141,7 +141,6 @@ Layout layout_of(const Geo &g, int64_t base) {
     L.runlab = take((int64_t)g.nb * g.runcap * 2);
     L.icomp = take((int64_t)g.nb * g.icap * 4);
     L.icount = take((int64_t)g.nb * 4);
-    L.ncanon = take(nodes * 4);
     L.nrun = take((int64_t)g.nb * 4);
     L.rowcnt = take((int64_t)g.rows * 4);
     L.blksum = take((int64_t)g.nblk * 4);
@@ -163,7 +162,6 @@ void bind(Geo *g, char *base, const Layout &L) {
     g->runlab = (uint16_t *)(base + L.runlab);
     g->icomp = (uint32_t *)(base + L.icomp);
     g->icount = (int32_t *)(base + L.icount);
-    g->ncanon = (int32_t *)(base + L.ncanon);
     g->nrun = (int32_t *)(base + L.nrun);
     g->rowcnt = (int32_t *)(base + L.rowcnt);
     g->blksum = (int32_t *)(base + L.blksum);

@@ -79,7 +79,6 @@ struct Geo {
     int32_t *nsize;   // [nb*cap] sites in the node; at a root, the cluster
     uint16_t *nlpos;  // [nb*cap] brick-local position row*64 + x of the key
     int64_t *nrootpos; // [nb*cap] word index << 6 | bit of the node's root key site
-    int32_t *ncanon;  // [nb*cap] final label of the node's cluster
     int32_t *nrun;    // [nb] runs of each brick
     uint16_t *runlab; // [nb][runcap] component slot of every run of the brick
     uint32_t *icomp;  // [nb][icap] interior component: size << LPOS_BITS | key position
@@ -1053,63 +1052,14 @@ __device__ __forceinline__ void phase_rowpre(const Geo &g, int blk, int32_t *tmp
 }
 
 // --------------------------------------------------------------------------
-// phase: canon -- final label of every node: 1 + rank of its cluster's root
-// site among all root sites in linear order (root bit words and per-word
-// prefixes); the root node also writes its cluster's size
-// --------------------------------------------------------------------------
-
-__device__ __forceinline__ void phase_canon(const Geo &g, int b) {
-    const int cnt = g.bcount[b];
-    const int nt = blockDim.x;
-    const int64_t kmax = (n_sites(g) + 1) / 2;
-    const int64_t words = (int64_t)g.nb * g.R;
-    // two nodes per thread and step, loads of both in flight together
-    for (int i0 = threadIdx.x; i0 < cnt; i0 += 2 * nt) {
-        const bool two = i0 + nt < cnt;
-        int64_t pos[2], wi[2];
-        int n[2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            n[u] = b * g.cap + i0 + (u && two ? nt : 0);
-            pos[u] = g.nrootpos[n[u]];
-            wi[u] = pos[u] >> 6;
-        }
-        uint64_t rw[2];
-        int wp[2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const bool ok = wi[u] >= 0 && wi[u] < words;
-            rw[u] = ok ? g.root[wi[u]] : 0ull;
-            wp[u] = ok ? g.wpre[wi[u]] : 0;
-        }
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            if (u == 1 && !two) break;
-            if (wi[u] < 0 || wi[u] >= words) {
-                set_err(g, ERR_RANGE);
-                continue;
-            }
-            const int rank = wp[u] + __popcll(rw[u] & mask_lt((int)(pos[u] & 63)));
-            g.ncanon[n[u]] = rank + 1;
-            const int lp = g.nlpos[n[u]];
-            // this node holds the cluster's key site: it is the root
-            if (g.sizes && wi[u] == (int64_t)b * g.R + min(lp >> 6, g.R - 1) && (pos[u] & 63) == (lp & 63)) {
-                if (rank >= 0 && (int64_t)rank < kmax)
-                    g.sizes[rank] = g.nsize[n[u]];
-                else
-                    set_err(g, ERR_RANGE);
-            }
-        }
-    }
-}
-
-// --------------------------------------------------------------------------
-// phase: write -- label of every component slot of the brick (node label for
-// boundary slots, 1 + rank of the key site for interior ones, whose sizes
-// are written here); then every site takes the label of its run's slot.
-// All global inputs are requested before the first wait: slot labels and
-// raw interior entries go to s.par[0, nc), run slots to s.par[nc, nc + nr)
-// when they fit (else they are read from global memory per site).
+// phase: write -- label of every component slot of the brick: 1 + rank of
+// the cluster's root key site, from the node's root for boundary slots and
+// from the brick's own words for interior ones; sizes are written by the
+// slot that holds its cluster's key site.  Then every site takes the label
+// of its run's slot.  The first global inputs are requested before the first
+// wait: root positions of the boundary nodes, raw interior entries (to
+// s.par[bc, nc)) and run slots (to s.par[nc, nc + nr) when they fit, else
+// they are read from global memory per site).
 // --------------------------------------------------------------------------
 
 // Expand run labels to sites, one lattice row per wave and one site per
@@ -1142,6 +1092,65 @@ __device__ __forceinline__ void write_rows(const Geo &g, const Brick &k, const L
     }
 }
 
+// The labels of the brick's boundary components, each the final label of its
+// cluster: 1 + the rank of the cluster's root key site among all root sites
+// in linear order (root bit words and per-word prefixes).  s.par[c] = 1 +
+// rank for c < bc; the node holding its cluster's key site also writes the
+// cluster's size.  A thread takes nodes c0 and c0 + WG at a
+// time; the first pair's root positions are loaded at the start of the
+// write phase together with its other first loads.
+struct CanonPair {
+    int64_t pos[2];
+    int lp[2];
+};
+
+__device__ __forceinline__ CanonPair canon_load(const Geo &g, int b, int c0, int ncl) {
+    CanonPair p;
+    const int n0 = b * g.cap;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int c = min(c0 + u * WG, ncl - 1);
+        p.pos[u] = c >= 0 ? g.nrootpos[n0 + c] : 0;
+        p.lp[u] = c >= 0 ? g.nlpos[n0 + c] : 0;
+    }
+    return p;
+}
+
+__device__ __forceinline__ void canon_rank(const Geo &g, int b, int c0, int ncl, const CanonPair &p, LdsBrick &s) {
+    const int64_t kmax = (n_sites(g) + 1) / 2;
+    const int64_t words = (int64_t)g.nb * g.R;
+    const int n0 = b * g.cap;
+    int64_t wi[2];
+    uint64_t rw[2];
+    int wp[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        wi[u] = p.pos[u] >> 6;
+        const bool ok = wi[u] >= 0 && wi[u] < words;
+        rw[u] = ok ? g.root[wi[u]] : 0ull;
+        wp[u] = ok ? g.wpre[wi[u]] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int c = c0 + u * WG;
+        if (c >= ncl) break;
+        if (wi[u] < 0 || wi[u] >= words) {
+            set_err(g, ERR_RANGE);
+            s.par[c] = 0;
+            continue;
+        }
+        const int rank = wp[u] + __popcll(rw[u] & mask_lt((int)(p.pos[u] & 63)));
+        s.par[c] = rank + 1;
+        // this node holds the cluster's key site: it is the root
+        if (g.sizes && wi[u] == (int64_t)b * g.R + min(p.lp[u] >> 6, g.R - 1) && (p.pos[u] & 63) == (p.lp[u] & 63)) {
+            if (rank >= 0 && (int64_t)rank < kmax)
+                g.sizes[rank] = g.nsize[n0 + c];
+            else
+                set_err(g, ERR_RANGE);
+        }
+    }
+}
+
 __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
     const Brick k = brick_of(g, b);
     const int t = threadIdx.x;
@@ -1149,6 +1158,9 @@ __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
     const int bc = g.bcount[b], nc = bc + g.icount[b], nr = g.nrun[b];
     const bool fit = nc + nr <= MAXRUNS;
     const uint16_t *L = g.runlab + (int64_t)b * g.runcap;
+    const int nbl = min(bc, MAXRUNS);  // boundary slots held in LDS
+    CanonPair first;
+    if (t < nbl) first = canon_load(g, b, t, nbl);
     uint64_t w = 0;
     if (t < R) {
         const int64_t i = (int64_t)b * R + t;
@@ -1168,12 +1180,13 @@ __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
             for (int u = 0; u < 4; ++u) {
                 const int c = c0 + u * WG;
                 v[u] = c >= ncl ? 0
-                       : c < bc ? g.ncanon[(int64_t)b * g.cap + c]
-                                : (int32_t)g.icomp[(int64_t)b * g.icap + (c - bc)];
+                       : c < bc ? 0 : (int32_t)g.icomp[(int64_t)b * g.icap + (c - bc)];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (c0 + u * WG < ncl) s.par[c0 + u * WG] = v[u];
+            for (int u = 0; u < 4; ++u) {
+                const int c = c0 + u * WG;
+                if (c >= bc && c < ncl) s.par[c] = v[u];
+            }
         }
         if (fit) {
             const uint64_t *L4 = reinterpret_cast<const uint64_t *>(L);
@@ -1191,6 +1204,8 @@ __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
                 }
             }
         }
+        if (t < nbl) canon_rank(g, b, t, nbl, first, s);
+        for (int c0 = t + 2 * WG; c0 < nbl; c0 += 2 * WG) canon_rank(g, b, c0, nbl, canon_load(g, b, c0, nbl), s);
     }
     int nruns;
     const int off = block_excl_scan(__popcll(run_starts(w)), s.tmp, &nruns);
@@ -1228,7 +1243,7 @@ __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
 // store of a phase as a possible write to them.
 // --------------------------------------------------------------------------
 
-constexpr int NPH = 8;  // local, merge, roots, rowsum, scanblk, rowpre, canon, write
+constexpr int NPH = 7;  // local, merge, roots, rowsum, scanblk, rowpre, write
 
 typedef const __attribute__((address_space(4))) Geo ConstGeo;
 typedef const __attribute__((address_space(4))) int32_t ConstI32;

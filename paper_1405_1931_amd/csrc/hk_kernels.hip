@@ -44,15 +44,14 @@ __global__ __launch_bounds__(WG) void k_rowpre(Geo g) {
     phase_rowpre(g, blockIdx.x, tmp);
 }
 
-__global__ __launch_bounds__(WG_NODES) void k_canon(Geo g) { phase_canon(g, blockIdx.x); }
 
 __global__ __launch_bounds__(WG) void k_write(Geo g) {
     __shared__ LdsBrick s;
     phase_write(g, blockIdx.x, s);
 }
 
-const char *const kPhaseNames[kPhases] = {"k_local",  "k_merge",  "k_roots", "k_rowsum",
-                                          "k_scanblk", "k_rowpre", "k_canon", "k_write"};
+const char *const kPhaseNames[kPhases] = {"k_local", "k_merge", "k_roots", "k_rowsum",
+                                          "k_scanblk", "k_rowpre", "k_write"};
 
 hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev, int pk) {
     const dim3 blk(WG), small(WG_NODES);
@@ -77,10 +76,8 @@ hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev, int pk) {
     mark(5);
     hipLaunchKernelGGL(k_rowpre, dim3(g.nblk), blk, 0, st, g);
     mark(6);
-    hipLaunchKernelGGL(k_canon, dim3(g.nb), small, 0, st, g);
-    mark(7);
     hipLaunchKernelGGL(k_write, dim3(g.nb), blk, 0, st, g);
-    mark(8);
+    mark(7);
     return hipGetLastError();
 }
 
