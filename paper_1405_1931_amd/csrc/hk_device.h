@@ -838,17 +838,24 @@ __device__ __forceinline__ void phase_merge(const Geo &g, int b, MergeLds &m) {
     const int bzn = k.bz > 0 ? b - g.nbx * g.nby : b + (g.nbz - 1) * g.nbx * g.nby;
     const int cx = k.hxl ? (g.R + 63) >> 6 : 0, cy = k.hyl ? g.BZ : 0, cz = k.hzl ? g.BY : 0;
     const int nch = cx + cy + cz;
-    for (int c0 = wv; c0 < nch; c0 += nw * MERGE_U) {
+    // each wave takes a contiguous run of chunks, so that on the y and z
+    // faces (one chunk per face row) a lane sees the site one row back and
+    // can drop a pair identical to the one recorded there: a cluster that
+    // crosses a face meets the same two components row after row
+    const int per = (nch + nw - 1) / nw;
+    const int cbeg = wv * per, cend = min(nch, cbeg + per);
+    uint16_t pa = NOSITE, pc = NOSITE;  // this lane's pair one face row back
+    for (int c0 = cbeg; c0 < cend; c0 += MERGE_U) {
         uint16_t fa[MERGE_U], fc[MERGE_U];
         bool pre[MERGE_U];
         int nbb[MERGE_U];
 #pragma unroll
         for (int u = 0; u < MERGE_U; ++u) {
-            const int c = c0 + u * nw;  // wave-uniform
+            const int c = c0 + u;  // wave-uniform
             fa[u] = fc[u] = NOSITE;
             pre[u] = false;
             nbb[u] = b;
-            if (c >= nch) continue;
+            if (c >= cend) continue;
             const uint16_t *Fs, *Gs;
             int e;
             bool valid;
@@ -885,8 +892,8 @@ __device__ __forceinline__ void phase_merge(const Geo &g, int b, MergeLds &m) {
         }
 #pragma unroll
         for (int u = 0; u < MERGE_U; ++u) {
-            const int c = c0 + u * nw;
-            if (c >= nch) continue;
+            const int c = c0 + u;
+            if (c >= cend) continue;
             const bool both = fa[u] != NOSITE && fc[u] != NOSITE;
             // was the previous site along the face a pair too?
             const int up = __shfl_up((int)both, 1, 64);
@@ -897,7 +904,13 @@ __device__ __forceinline__ void phase_merge(const Geo &g, int b, MergeLds &m) {
             } else {
                 prev = lane > 0 && up != 0;
             }
-            if (both && !prev) {
+            // the previous chunk of this wave is the face row just before (a
+            // chunk of the same y or z face), or the pair carried is NOSITE
+            const bool first_row = c == cx || c == cx + cy;
+            const bool vert = c > cx && !first_row && c > cbeg && fa[u] == pa && fc[u] == pc;
+            pa = fa[u];
+            pc = fc[u];
+            if (both && !prev && !vert) {
                 const int na = b * g.cap + fa[u], nc = nbb[u] * g.cap + fc[u];
                 const int i = atomicAdd(&m.count, 1);
                 if (i < MERGE_CAP)
