@@ -327,6 +327,56 @@ def bench_droplets(hk, torch, reps=50, r_max=40.0, n_bins=80):
     return out
 
 
+def bench_incremental(hk, torch, phi, mask, reps=10, boxes=64, seed=12):
+    """A slowly moving field: the workload field A and a copy B with `boxes`
+    3x3x3 boxes flipped in sign at random places (so that each call sees the
+    occupancy of a few hundred bricks change), labelled alternately.  Times
+    hk_label and an incremental state (hk_incr_label) over the same sequence
+    (HIP events on the launch stream) and checks that both give the same
+    labels."""
+    import numpy as np
+
+    nz, ny, nx = phi.shape
+    rng = np.random.default_rng(seed)
+    other = phi.clone()
+    for _ in range(boxes):
+        z, y, x = (int(rng.integers(0, n - 3)) for n in (nz, ny, nx))
+        other[z:z + 3, y:y + 3, x:x + 3] *= -1.0
+    fields = [phi, other]
+    labels = torch.empty_like(phi, dtype=torch.int32)
+    ref = torch.empty_like(phi, dtype=torch.int32)
+    kbuf = torch.zeros(1, dtype=torch.int64, device="cuda")
+    sizes = torch.empty(max(1, hk.max_clusters(nx, ny, nz)), dtype=torch.int64, device="cuda")
+    rel = torch.zeros(1, dtype=torch.int64, device="cuda")
+    out = {"workload": f"percolation {nx}x{ny}x{nz} mask {mask}, alternating with a copy with {boxes} "
+                       f"3x3x3 boxes flipped"}
+
+    def timed(fn):
+        for i in range(4):
+            fn(i)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(reps):
+            fn(i)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out["full_ms"] = round(timed(lambda i: hk.label_into(fields[i % 2], mask, labels, kbuf, sizes)), 4)
+    with hk.Incremental(phi.shape, mask) as st:
+        out["incremental_ms"] = round(timed(lambda i: st.label_into(fields[i % 2], labels, kbuf, sizes, rel)), 4)
+        out["bricks_relabelled"] = int(rel.item())
+        last = fields[(reps + 3) % 2]
+        hk.label_into(last, mask, ref, kbuf, sizes)
+        assert torch.equal(labels, ref), "incremental labels differ from hk_label"
+        assert st.device_error() == 0
+    out["speedup"] = round(out["full_ms"] / out["incremental_ms"], 2)
+    out["gsites_per_s"] = round(phi.numel() / out["incremental_ms"] / 1e6, 2)
+    del other
+    return out
+
+
 def calibration_copy(torch, nbytes=1 << 30):
     """One plain device copy of `nbytes` (read nbytes + write nbytes), for
     scaling the HBM byte counters of a counter run."""
@@ -465,9 +515,9 @@ def traffic_table(fetch_dir, write_dir, tag, calib_bytes):
     lines = [f"# HBM traffic per kernel, hk_label, workload {tag}", "",
              "commands (from /tmp with TMPDIR=/tmp on the MI355X box; one counter per run):", "",
              f"    rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fetch_dir} -o run -- python3 bench.py "
-             "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-served --no-classify --no-droplets --no-profile --calib-copy",
+             "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-served --no-classify --no-droplets --no-incremental --no-profile --calib-copy",
              f"    rocprofv3 --pmc WRITE_SIZE --output-format csv -d {write_dir} -o run -- python3 bench.py "
-             "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-served --no-classify --no-droplets --no-profile --calib-copy",
+             "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-served --no-classify --no-droplets --no-incremental --no-profile --calib-copy",
              f"    python bench.py --summarize-pmc {fetch_dir} {write_dir} <kernel> {tag}", "",
              f"calibration: a {calib_bytes / 2**30:.0f} GiB device copy reads FETCH_SIZE "
              f"{1 / fac['FETCH_SIZE']:.4f}x and WRITE_SIZE {1 / fac['WRITE_SIZE']:.4f}x its size; the counts below are "
@@ -497,6 +547,7 @@ def main():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--no-classify", action="store_true")
     ap.add_argument("--no-droplets", action="store_true")
+    ap.add_argument("--no-incremental", action="store_true")
     ap.add_argument("--calib-copy", action="store_true", help="run one 1 GiB device copy (counter calibration)")
     ap.add_argument("--summarize-trace", metavar="DB",
                     help="write the per-section kernel summaries to profiles/ from a rocprofv3 trace database and exit")
@@ -622,6 +673,10 @@ def main():
         torch.cuda.empty_cache()
         result["droplets"] = bench_droplets(hk, torch)
         log(f"droplets: {result['droplets']}")
+    if not args.no_incremental:
+        torch.cuda.empty_cache()
+        result["incremental"] = bench_incremental(hk, torch, phi, mask)
+        log(f"incremental: {result['incremental']}")
     if not args.no_cpu_baseline:
         planes = min(args.cpu_planes, edge)
         result["cpu_baseline"] = cpu_baseline(phi_np, mask, planes)

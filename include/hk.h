@@ -98,6 +98,37 @@ typedef enum {
 int hk_label_pred(const void *field, int32_t predicate, float param, int32_t nx, int32_t ny, int32_t nz,
                   uint32_t periodic_mask, int32_t *labels, int64_t *n_clusters, int64_t *sizes, hipStream_t stream);
 
+/*
+ * Incremental relabelling of a field that changes little from one call to
+ * the next (a lattice-Boltzmann field between time steps, Sec. 5 and 6: the
+ * labelling runs every step on a slowly moving interface).  A state object
+ * owns a workspace for one lattice shape and keeps, between calls, each
+ * brick's local labelling; a call labels anew only the bricks whose
+ * occupancy changed since the previous call on the same state, restores the
+ * others, and runs the global phases over all.  Every call's outputs are
+ * identical to what hk_label gives for the same field.
+ *
+ * hk_incr_create: a state for [nz][ny][nx] lattices with the given periodic
+ *   mask, on the current device; *out receives it (NULL on error).  The
+ *   workspace is allocated here (hipMalloc), about the size of hk_label's
+ *   plus 12 B per node slot and 8 B per brick row.  Errors as for hk_label,
+ *   HK_ERR_HIP when the allocation fails.
+ * hk_incr_label: label `phi` ([nz][ny][nx] float32, device) into labels,
+ *   n_clusters and sizes as hk_label does.  relabelled: one int64, device,
+ *   out, or NULL: the number of bricks labelled anew by this call (all of
+ *   them on the first call).  Calls on one state must be on its device and
+ *   must not overlap (one stream, or ordered by the caller); the first call
+ *   labels every brick.  Nothing is allocated.
+ * hk_incr_device_error: as hk_device_error, for the state's own check flag.
+ * hk_incr_destroy: synchronise the state's device and free the state.
+ */
+typedef struct hk_incr hk_incr;
+int hk_incr_create(int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask, hk_incr **out);
+int hk_incr_label(hk_incr *state, const float *phi, int32_t *labels, int64_t *n_clusters, int64_t *sizes,
+                  int64_t *relabelled, hipStream_t stream);
+int hk_incr_device_error(hk_incr *state, hipStream_t stream, int32_t *code);
+void hk_incr_destroy(hk_incr *state);
+
 /* One lattice of a batch; fields as in hk_label. */
 typedef struct {
     const float *phi;

@@ -129,6 +129,63 @@ def label_pred(field, predicate, param=0.0, periodic=0, stream=None):
     return labels, kk, sz[:kk]
 
 
+class Incremental:
+    """Incremental relabelling state for one lattice shape (hk_incr_*): each
+    call labels anew only the bricks whose occupancy changed since the
+    previous call, with outputs identical to label()."""
+
+    def __init__(self, shape, periodic=0):
+        nz, ny, nx = (int(v) for v in shape)
+        h = ctypes.c_void_p()
+        _lib.check(_lib.load().hk_incr_create(nx, ny, nz, mask_of(periodic), ctypes.byref(h)), "hk_incr_create")
+        self._h = h
+        self.shape = (nz, ny, nx)
+        self.mask = mask_of(periodic)
+
+    def label_into(self, phi, labels, n_clusters, sizes=None, relabelled=None, stream=None):
+        """Enqueue one call; relabelled: int64 device tensor for the number of
+        bricks labelled anew, or None."""
+        _check_phi(phi)
+        if tuple(phi.shape) != self.shape:
+            raise ValueError(f"phi has shape {tuple(phi.shape)}, the state was made for {self.shape}")
+        if self._h is None:
+            raise RuntimeError("the state is closed")
+        rc = _lib.load().hk_incr_label(self._h, phi.data_ptr(), labels.data_ptr(), n_clusters.data_ptr(),
+                                       sizes.data_ptr() if sizes is not None else None,
+                                       relabelled.data_ptr() if relabelled is not None else None,
+                                       _stream_handle(stream))
+        _lib.check(rc, "hk_incr_label")
+
+    def label(self, phi, stream=None):
+        """(labels, K, sizes[K], bricks labelled anew); synchronises for K."""
+        import torch
+
+        nz, ny, nx = self.shape
+        labels = torch.empty(self.shape, dtype=torch.int32, device=phi.device)
+        k = torch.zeros(1, dtype=torch.int64, device=phi.device)
+        sz = torch.empty(max(1, max_clusters(nx, ny, nz)), dtype=torch.int64, device=phi.device)
+        rel = torch.zeros(1, dtype=torch.int64, device=phi.device)
+        self.label_into(phi, labels, k, sz, rel, stream=stream)
+        kk = int(k.item())
+        return labels, kk, sz[:kk], int(rel.item())
+
+    def device_error(self, stream=None) -> int:
+        code = ctypes.c_int32(0)
+        _lib.load().hk_incr_device_error(self._h, _stream_handle(stream), ctypes.byref(code))
+        return code.value
+
+    def close(self):
+        if self._h is not None:
+            _lib.load().hk_incr_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
 def _jobs_array(jobs):
     arr = (_lib.HkJob * max(1, len(jobs)))()
     for i, j in enumerate(jobs):

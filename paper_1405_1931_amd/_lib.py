@@ -66,6 +66,10 @@ _SIGS = {
     "hk_label": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "hk_label_pred": (ctypes.c_int, [_P, _I32, ctypes.c_float, _I32, _I32, _I32, ctypes.c_uint32, _P, _P, _P, _P]),
+    "hk_incr_create": (ctypes.c_int, [_I32, _I32, _I32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]),
+    "hk_incr_label": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "hk_incr_device_error": (ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int32)]),
+    "hk_incr_destroy": (None, [_P]),
     "hk_label_batched": (ctypes.c_int, [ctypes.POINTER(HkJob), ctypes.c_int32, ctypes.c_void_p]),
     "hk_max_clusters": (ctypes.c_int64, [ctypes.c_int32] * 3),
     "hk_workspace_bytes": (ctypes.c_int64, [ctypes.c_int32] * 3),

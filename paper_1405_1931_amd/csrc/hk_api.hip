@@ -380,6 +380,92 @@ int hk_label_pred(const void *field, int32_t predicate, float param, int32_t nx,
     return label_one(field, pk, order_key(pb), nx, ny, nz, periodic_mask, labels, n_clusters, sizes, stream);
 }
 
+// ------------------------------------------------------------ incremental
+
+struct hk_incr {
+    int device = 0;
+    hk::Geo g;           // geometry and workspace pointers (caller buffers unset)
+    char *base = nullptr;
+    bool primed = false; // a labelling has run: the saved tables are valid
+};
+
+int hk_incr_create(int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask, hk_incr **out) {
+    if (!out) return HK_ERR_INVALID_ARG;
+    *out = nullptr;
+    int rc = check_shape(nx, ny, nz, periodic_mask);
+    if (rc != HK_OK) return rc;
+    Geo g;
+    rc = plan_lattice(nx, ny, nz, periodic_mask, &g);
+    if (rc != HK_OK) return rc;
+    const Layout L = layout_of(g, 0);
+    const int64_t words = (int64_t)g.nb * g.R, nodes = (int64_t)g.nb * g.cap;
+    const int64_t o_nsize0 = kErrBytes + L.total;
+    const int64_t o_rootw0 = align_up(o_nsize0 + nodes * 4);
+    const int64_t total = align_up(o_rootw0 + words * 8);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HK_ERR_HIP;
+    void *p = nullptr;
+    if (hipMalloc(&p, (size_t)total) != hipSuccess) return HK_ERR_HIP;
+    if (hipMemset(p, 0, (size_t)kErrBytes) != hipSuccess) {
+        (void)hipFree(p);
+        return HK_ERR_HIP;
+    }
+    hk_incr *st = new hk_incr;
+    st->device = dev;
+    st->base = (char *)p;
+    st->g = g;
+    st->g.err = (int32_t *)st->base;
+    bind(&st->g, st->base + kErrBytes, L);
+    st->g.nsize0 = (int32_t *)(st->base + o_nsize0);
+    st->g.rootw0 = (uint64_t *)(st->base + o_rootw0);
+    *out = st;
+    return HK_OK;
+}
+
+int hk_incr_label(hk_incr *st, const float *phi, int32_t *labels, int64_t *n_clusters, int64_t *sizes,
+                  int64_t *relabelled, hipStream_t stream) {
+    if (!st || !phi || !labels || !n_clusters) return HK_ERR_INVALID_ARG;
+    if ((const void *)labels == (const void *)phi) return HK_ERR_INVALID_ARG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HK_ERR_HIP;
+    if (dev != st->device) return HK_ERR_INVALID_ARG;
+    Geo g = st->g;
+    g.phi = phi;
+    g.tkey = 0;
+    g.labels = labels;
+    g.n_clusters = n_clusters;
+    g.sizes = sizes;
+    g.incr = st->primed ? 2 : 1;
+    g.nchanged = relabelled;
+    (void)hipGetLastError();
+    if (relabelled) hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(64), 0, stream, relabelled);
+    hipEvent_t *ev = profile_events();
+    if (launch_single(g, stream, ev, PK_GT0) != hipSuccess) return HK_ERR_HIP;
+    st->primed = true;
+    return HK_OK;
+}
+
+int hk_incr_device_error(hk_incr *st, hipStream_t stream, int32_t *code) {
+    if (!st) return HK_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(stream) != hipSuccess) return HK_ERR_HIP;
+    int32_t v = 0;
+    if (hipMemcpy(&v, st->g.err, sizeof v, hipMemcpyDeviceToHost) != hipSuccess) return HK_ERR_HIP;
+    if (code) *code = v;
+    if (v && hipMemset(st->g.err, 0, sizeof v) != hipSuccess) return HK_ERR_HIP;
+    return v ? HK_ERR_DEVICE : HK_OK;
+}
+
+void hk_incr_destroy(hk_incr *st) {
+    if (!st) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(st->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(st->base);
+    (void)hipSetDevice(cur);
+    delete st;
+}
+
 int hk_reserve(int64_t bytes, hipStream_t stream) {
     if (bytes < 0) return HK_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(g_ws_mu);

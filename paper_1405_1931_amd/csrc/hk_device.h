@@ -88,6 +88,14 @@ struct Geo {
     int32_t *rowcnt;  // [rows] roots per lattice row
     int32_t *blksum;  // [nblk] roots per block of rows, then their prefix
     int32_t *err;     // sticky check flag
+    // incremental relabelling of a field that changes little between calls:
+    // 0 off; 1 label every brick and keep the copies below; 2 as 1, but a
+    // brick whose occupancy words equal those of the previous call keeps its
+    // local labelling (node, interior component, run and face tables)
+    int32_t incr;
+    int32_t *nsize0;    // [nb*cap] size of each node's brick-local component
+    uint64_t *rootw0;   // [nb][R] root bits of each brick's interior components
+    int64_t *nchanged;  // bricks labelled anew by the call, or null
 };
 
 __host__ __device__ __forceinline__ int n_nodes(const Geo &g) { return g.nb * g.cap; }
@@ -684,6 +692,22 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
     const int R = g.R;
     if (t < R) s.rootw[t] = 0ull;
     __syncthreads();
+    if (g.incr == 2) {
+        // the same words give the same local labelling: restore only what
+        // the later phases modify (node parents and sizes, the root bits)
+        const bool diff = t < R && g.occ[(int64_t)b * R + t] != s.occ[t];
+        if (!__syncthreads_or(diff)) {
+            const int bc = g.bcount[b];
+            for (int c = t; c < bc; c += WG) {
+                const int n = b * g.cap + c;
+                g.npar[n] = n;
+                g.nsize[n] = g.nsize0[n];
+            }
+            if (t < R) g.root[(int64_t)b * R + t] = g.rootw0[(int64_t)b * R + t];
+            return;
+        }
+    }
+    if (g.incr != 0 && t == 0 && g.nchanged) atomicAdd((unsigned long long *)g.nchanged, 1ull);
     if (t < R) g.occ[(int64_t)b * R + t] = s.occ[t];  // the words, for the later phases
     const CoreOut co = brick_core(g, k, s);
 
@@ -712,6 +736,7 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
                         g.nkey[n] = (k.x0 + sb) + g.nx * ((k.y0 + yl) + g.ny * (k.z0 + zl));
                         g.nlpos[n] = (uint16_t)(row * 64 + sb);
                         g.nsize[n] = -1 - v;
+                        if (g.incr != 0) g.nsize0[n] = -1 - v;
                         g.npar[n] = n;
                     } else {
                         set_err(g, ERR_CAP);
@@ -737,7 +762,10 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
         g.nrun[b] = min(co.nruns, g.runcap);
     }
     __syncthreads();
-    if (t < R) g.root[(int64_t)b * R + t] = s.rootw[t];
+    if (t < R) {
+        g.root[(int64_t)b * R + t] = s.rootw[t];
+        if (g.incr != 0) g.rootw0[(int64_t)b * R + t] = s.rootw[t];
+    }
 
     // component slot of every run, for the final pass
     uint16_t *L = g.runlab + (int64_t)b * g.runcap;

@@ -50,6 +50,10 @@ __global__ __launch_bounds__(WG) void k_write(Geo g) {
     phase_write(g, blockIdx.x, s);
 }
 
+__global__ void k_zero_i64(int64_t *p) {
+    if (threadIdx.x == 0) *p = 0;
+}
+
 const char *const kPhaseNames[kPhases] = {"k_local", "k_merge", "k_roots", "k_rowsum",
                                           "k_scanblk", "k_rowpre", "k_write"};
 

@@ -15,4 +15,7 @@ extern const char *const kPhaseNames[kPhases];
 // `pk` selects the occupancy predicate (PK_*) of the brick phase
 hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev, int pk = PK_GT0);
 
+// *p = 0 on the stream (one thread)
+__global__ void k_zero_i64(int64_t *p);
+
 }  // namespace hk

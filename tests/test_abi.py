@@ -150,3 +150,16 @@ def test_label_pred_argument_errors_without_gpu(lib):
     assert lib.hk_label_pred(dummy, 1, 0.0, 4, 4, 4, 8, other, other, None, None) == _lib.HK_ERR_INVALID_ARG
     assert lib.hk_label_pred(dummy, 0, 0.5, 4, 4, 4, 0, dummy, other, None, None) == _lib.HK_ERR_INVALID_ARG
     assert lib.hk_label_pred(dummy, 0, 0.5, 2048, 2048, 1024, 0, other, other, None, None) == _lib.HK_ERR_TOO_LARGE
+
+
+def test_incremental_argument_errors_without_gpu(lib):
+    out = ctypes.c_void_p()
+    assert lib.hk_incr_create(0, 4, 4, 0, ctypes.byref(out)) == _lib.HK_ERR_INVALID_ARG
+    assert out.value is None
+    assert lib.hk_incr_create(4, 4, 4, 9, ctypes.byref(out)) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_incr_create(2048, 2048, 1024, 0, ctypes.byref(out)) == _lib.HK_ERR_TOO_LARGE
+    assert lib.hk_incr_create(4, 4, 4, 0, None) == _lib.HK_ERR_INVALID_ARG
+    dummy = ctypes.c_void_p(0x1000)
+    assert lib.hk_incr_label(None, dummy, dummy, dummy, None, None, None) == _lib.HK_ERR_INVALID_ARG
+    assert lib.hk_incr_device_error(None, None, None) == _lib.HK_ERR_INVALID_ARG
+    lib.hk_incr_destroy(None)  # a no-op
