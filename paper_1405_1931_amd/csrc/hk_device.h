@@ -1129,7 +1129,9 @@ __device__ __forceinline__ void write_rows(const Geo &g, const Brick &k, const L
             const int slot = RUNS_IN_LDS ? s.par[nc + run] : L[run];
             lab = s.par[min(slot, MAXRUNS - 1)];
         }
-        if (lane < k.ex) row[lane] = lab;
+        // the labels are written once and read by nobody in this call:
+        // a streaming store, which does not keep the lines in L2
+        if (lane < k.ex) __builtin_nontemporal_store(lab, row + lane);
     }
 }
 
