@@ -377,6 +377,40 @@ def bench_incremental(hk, torch, phi, mask, reps=10, boxes=64, seed=12):
     return out
 
 
+def bench_cluster_sweep(hk, torch, n=1024, mask=7, reps=5):
+    """The Sec. 3 benchmark lattice: block checkerboards of n^3 sites with
+    blocks of b^3 (b = 1 .. 64), so that K runs from n^3/2 (the V/2 bound)
+    down to (n/64)^3/2; time per labelling against K (HIP events on the
+    launch stream).  K is checked against its closed form."""
+    a = torch.arange(n, device="cuda", dtype=torch.int32)
+    z, y, x = a.view(n, 1, 1), a.view(1, n, 1), a.view(1, 1, n)
+    labels = torch.empty((n, n, n), dtype=torch.int32, device="cuda")
+    kbuf = torch.zeros(1, dtype=torch.int64, device="cuda")
+    sizes = torch.empty(hk.max_clusters(n, n, n), dtype=torch.int64, device="cuda")
+    points = []
+    for b in (1, 2, 4, 8, 16, 32, 64):
+        par = (torch.div(x, b, rounding_mode="floor") + torch.div(y, b, rounding_mode="floor")
+               + torch.div(z, b, rounding_mode="floor")) & 1
+        phi = torch.where(par == 0, 1.0, -1.0).to(torch.float32)
+        del par
+        for _ in range(2):
+            hk.label_into(phi, mask, labels, kbuf, sizes)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            hk.label_into(phi, mask, labels, kbuf, sizes)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        k = int(kbuf.item())
+        assert k == (n // b) ** 3 // 2, f"block {b}: K = {k}"
+        points.append({"block": b, "clusters": k, "ms": round(ms, 4), "gsites_per_s": round(n ** 3 / ms / 1e6, 2)})
+        del phi
+    assert hk.device_error() == 0
+    return {"workload": f"block checkerboard {n}^3 mask {mask}, blocks b^3", "points": points}
+
+
 def calibration_copy(torch, nbytes=1 << 30):
     """One plain device copy of `nbytes` (read nbytes + write nbytes), for
     scaling the HBM byte counters of a counter run."""
@@ -515,9 +549,9 @@ def traffic_table(fetch_dir, write_dir, tag, calib_bytes):
     lines = [f"# HBM traffic per kernel, hk_label, workload {tag}", "",
              "commands (from /tmp with TMPDIR=/tmp on the MI355X box; one counter per run):", "",
              f"    rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fetch_dir} -o run -- python3 bench.py "
-             "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-served --no-classify --no-droplets --no-incremental --no-profile --calib-copy",
+             "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-served --no-classify --no-droplets --no-incremental --no-sweep --no-profile --calib-copy",
              f"    rocprofv3 --pmc WRITE_SIZE --output-format csv -d {write_dir} -o run -- python3 bench.py "
-             "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-served --no-classify --no-droplets --no-incremental --no-profile --calib-copy",
+             "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-served --no-classify --no-droplets --no-incremental --no-sweep --no-profile --calib-copy",
              f"    python bench.py --summarize-pmc {fetch_dir} {write_dir} <kernel> {tag}", "",
              f"calibration: a {calib_bytes / 2**30:.0f} GiB device copy reads FETCH_SIZE "
              f"{1 / fac['FETCH_SIZE']:.4f}x and WRITE_SIZE {1 / fac['WRITE_SIZE']:.4f}x its size; the counts below are "
@@ -548,6 +582,7 @@ def main():
     ap.add_argument("--no-classify", action="store_true")
     ap.add_argument("--no-droplets", action="store_true")
     ap.add_argument("--no-incremental", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the block-checkerboard cluster-count sweep")
     ap.add_argument("--calib-copy", action="store_true", help="run one 1 GiB device copy (counter calibration)")
     ap.add_argument("--summarize-trace", metavar="DB",
                     help="write the per-section kernel summaries to profiles/ from a rocprofv3 trace database and exit")
@@ -677,6 +712,10 @@ def main():
         torch.cuda.empty_cache()
         result["incremental"] = bench_incremental(hk, torch, phi, mask)
         log(f"incremental: {result['incremental']}")
+    if not args.no_sweep:
+        torch.cuda.empty_cache()
+        result["cluster_sweep"] = bench_cluster_sweep(hk, torch, n=edge)
+        log(f"cluster sweep: {result['cluster_sweep']}")
     if not args.no_cpu_baseline:
         planes = min(args.cpu_planes, edge)
         result["cpu_baseline"] = cpu_baseline(phi_np, mask, planes)
