@@ -111,7 +111,7 @@ int hk_label_pred(const void *field, int32_t predicate, float param, int32_t nx,
  * hk_incr_create: a state for [nz][ny][nx] lattices with the given periodic
  *   mask, on the current device; *out receives it (NULL on error).  The
  *   workspace is allocated here (hipMalloc), about the size of hk_label's
- *   plus 12 B per node slot and 8 B per brick row.  Errors as for hk_label,
+ *   plus 4 B per node slot and 8 B per brick row.  Errors as for hk_label,
  *   HK_ERR_HIP when the allocation fails.
  * hk_incr_label: label `phi` ([nz][ny][nx] float32, device) into labels,
  *   n_clusters and sizes as hk_label does.  relabelled: one int64, device,
