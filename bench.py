@@ -422,7 +422,7 @@ def calibration_copy(torch, nbytes=1 << 30):
     del a, b
 
 
-TRACE_CMD = ("cd /tmp && TMPDIR=/tmp rocprofv3 --kernel-trace --stats -d /root/repo/gpurun_out/prof -o run -- "
+TRACE_CMD = ("cd /tmp && TMPDIR=/tmp rocprofv3 --kernel-trace --stats -d <outdir> -o run -- "
              "python3 /root/repo/bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-batched --no-served")
 
 
@@ -465,8 +465,8 @@ def summarize_trace(db):
             a = agg.setdefault((n, gx // wx), [])
             a.append((e - s) / 1e3)
         tot = sum(sum(v) for v in agg.values())
-        lines = [f"# {title}", "", "command (on the MI355X box; the trace is split into the bench's sections by",
-                 "dispatch order with `python bench.py --summarize-trace <run_results.db>`):", "",
+        lines = [f"# {title}", "", "command (on an MI355X; the trace is split into the bench's sections by",
+                 "dispatch order with `python bench.py --summarize-trace <outdir>/run_results.db`):", "",
                  f"    {TRACE_CMD}", "",
                  f"{'kernel':<44} {'groups':>8} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}"]
         for (n, groups), v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
@@ -547,12 +547,12 @@ def traffic_table(fetch_dir, write_dir, tag, calib_bytes):
         e["rd" if counter == "FETCH_SIZE" else "wr"] += v["bytes"] * fac[counter] / 1e9
         e["us"].append(v["us"])
     lines = [f"# HBM traffic per kernel, hk_label, workload {tag}", "",
-             "commands (from /tmp with TMPDIR=/tmp on the MI355X box; one counter per run):", "",
-             f"    rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fetch_dir} -o run -- python3 bench.py "
+             "commands (from /tmp with TMPDIR=/tmp on an MI355X; one counter per run):", "",
+             "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <fetch_dir> -o run -- python3 bench.py "
              "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-served --no-classify --no-droplets --no-incremental --no-sweep --no-profile --calib-copy",
-             f"    rocprofv3 --pmc WRITE_SIZE --output-format csv -d {write_dir} -o run -- python3 bench.py "
+             "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <write_dir> -o run -- python3 bench.py "
              "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-served --no-classify --no-droplets --no-incremental --no-sweep --no-profile --calib-copy",
-             f"    python bench.py --summarize-pmc {fetch_dir} {write_dir} <kernel> {tag}", "",
+             f"    python bench.py --summarize-pmc <fetch_dir> <write_dir> <kernel> {tag}", "",
              f"calibration: a {calib_bytes / 2**30:.0f} GiB device copy reads FETCH_SIZE "
              f"{1 / fac['FETCH_SIZE']:.4f}x and WRITE_SIZE {1 / fac['WRITE_SIZE']:.4f}x its size; the counts below are "
              f"scaled by {fac['FETCH_SIZE']:.4f} (fetch) and {fac['WRITE_SIZE']:.4f} (write).", "",
