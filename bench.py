@@ -147,7 +147,27 @@ def bench_batched(hk, torch, warmup, reps):
     out["jobs"] = len(bufs)
     out["sites"] = total
     assert hk.device_error() == 0
+    out["cpu_baseline"] = stream_cpu_baseline(jobs, total)
     return out, bufs
+
+
+def stream_cpu_baseline(jobs, total):
+    """The serial oracle over every lattice of the stream, the lattices spread
+    over all host cores (threads: the oracle's C call releases the GIL)."""
+    import concurrent.futures as cf
+
+    import oracle
+
+    lib = oracle.load()
+    workers = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(workers) as ex:
+        list(ex.map(lambda j: oracle.label(j.phi, j.mask, lib=lib)[1], jobs))
+    dt = time.perf_counter() - t0
+    return {"value": round(len(jobs) / dt, 1), "unit": "jobs/s", "gsites_per_s": round(total / dt / 1e9, 4),
+            "cores": workers, "kind": "oracle",
+            "sample": f"all {len(jobs)} lattices of the stream ({total} sites), serial C oracle per lattice, "
+                      f"{workers} threads, {dt:.2f} s"}
 
 
 def bench_served(hk, torch, bufs, capacity_jobs_s, runs=4, slots=3, max_batch=64):
@@ -323,6 +343,62 @@ def bench_droplets(hk, torch, reps=50, r_max=40.0, n_bins=80):
     s_np = sizes[:k].cpu().numpy()
     exp = D.stats(s_np, 1, r_max, n_bins)
     assert hist.cpu().tolist() == exp[0].tolist() and c == [exp[1], exp[2]], "droplet statistics differ from the oracle"
+    assert hk.device_error() == 0
+    return out
+
+
+def event_times(torch, fn, reps):
+    """Per-call times (ms) of fn, each bracketed by HIP events on the launch
+    stream."""
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return ts
+
+
+def stats(ts):
+    s = sorted(ts)
+    return {"median_ms": round(s[len(s) // 2], 4), "min_ms": round(s[0], 4),
+            "p90_ms": round(s[min(len(s) - 1, int(0.9 * len(s)))], 4), "calls": len(s)}
+
+
+def copy_ceiling(torch, phi, reps=5):
+    """A plain device copy of the field (read 4N + write 4N bytes): the HBM
+    rate the same GPU reaches on the traffic pattern of labelling at best."""
+    dst = torch.empty_like(phi)
+    dst.copy_(phi)
+    torch.cuda.synchronize()
+    ms = sorted(event_times(torch, lambda: dst.copy_(phi), reps))[reps // 2]
+    del dst
+    return 2 * phi.numel() * 4 / ms / 1e6  # GB/s
+
+
+def bench_configs(hk, torch, reps=20):
+    """Configs 1 (64^3 percolation), 2 (512^3 droplets) and 4 (capsules
+    256x256x512) labelled alone: per-call median, min and p90."""
+    from paper_1405_1931_amd import workloads as W
+
+    out = {}
+    for cid in (1, 2, 4):
+        phi_np, mask = W.config(cid)
+        phi = torch.from_numpy(phi_np).cuda()
+        nz, ny, nx = phi.shape
+        labels = torch.empty_like(phi, dtype=torch.int32)
+        kbuf = torch.zeros(1, dtype=torch.int64, device="cuda")
+        sizes = torch.empty(max(1, hk.max_clusters(nx, ny, nz)), dtype=torch.int64, device="cuda")
+        fn = lambda: hk.label_into(phi, mask, labels, kbuf, sizes)
+        for _ in range(3):
+            fn()
+        st = stats(event_times(torch, fn, reps))
+        st.update({"workload": f"config {cid}: {nx}x{ny}x{nz} mask {mask}", "clusters": int(kbuf.item()),
+                   "gsites_per_s": round(phi.numel() / st["median_ms"] / 1e6, 2)})
+        out[f"config{cid}"] = st
+        del phi, labels, sizes
     assert hk.device_error() == 0
     return out
 
@@ -549,9 +625,9 @@ def traffic_table(fetch_dir, write_dir, tag, calib_bytes):
     lines = [f"# HBM traffic per kernel, hk_label, workload {tag}", "",
              "commands (from /tmp with TMPDIR=/tmp on an MI355X; one counter per run):", "",
              "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <fetch_dir> -o run -- python3 bench.py "
-             "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-served --no-classify --no-droplets --no-incremental --no-sweep --no-profile --calib-copy",
+             "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-served --no-classify --no-droplets --no-incremental --no-sweep --no-configs --no-profile --calib-copy",
              "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <write_dir> -o run -- python3 bench.py "
-             "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-served --no-classify --no-droplets --no-incremental --no-sweep --no-profile --calib-copy",
+             "--steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-served --no-classify --no-droplets --no-incremental --no-sweep --no-configs --no-profile --calib-copy",
              f"    python bench.py --summarize-pmc <fetch_dir> <write_dir> <kernel> {tag}", "",
              f"calibration: a {calib_bytes / 2**30:.0f} GiB device copy reads FETCH_SIZE "
              f"{1 / fac['FETCH_SIZE']:.4f}x and WRITE_SIZE {1 / fac['WRITE_SIZE']:.4f}x its size; the counts below are "
@@ -583,6 +659,7 @@ def main():
     ap.add_argument("--no-droplets", action="store_true")
     ap.add_argument("--no-incremental", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the block-checkerboard cluster-count sweep")
+    ap.add_argument("--no-configs", action="store_true", help="skip configs 1, 2 and 4 labelled alone")
     ap.add_argument("--calib-copy", action="store_true", help="run one 1 GiB device copy (counter calibration)")
     ap.add_argument("--summarize-trace", metavar="DB",
                     help="write the per-section kernel summaries to profiles/ from a rocprofv3 trace database and exit")
@@ -665,6 +742,15 @@ def main():
         log(f"kernels (ms/launch): {kernels}")
 
     path_bytes = 8 * n + 8 * k + 8
+    # per-call statistics of the same workload, and the copy ceiling (with
+    # the profiling pass: a counter run keeps the calibration copy the
+    # largest copy of the run)
+    path_gbs = path_bytes / (ms / 1e3) / 1e9
+    step_stats, copy_gbs = None, None
+    if not args.no_profile:
+        step_stats = stats(event_times(torch, lambda: hk.label_into(phi, mask, labels, kbuf, sizes), 10))
+        copy_gbs = copy_ceiling(torch, phi)
+        log(f"per call: {step_stats}; copy ceiling {copy_gbs:.0f} GB/s")
     result = {
         "metric": "Gsites/s labelled (1024^3 percolation p=0.3116, periodic)",
         "value": round(n / (ms / 1e3) / 1e9, 3),
@@ -680,11 +766,13 @@ def main():
         "data": "synthetic (seeded numpy PCG64 percolation field, resident in HBM)",
         "config": {"workload": f"site percolation {edge}^3 p=0.3116 periodic xyz", "nx": edge, "ny": edge,
                    "nz": edge, "periodic_mask": mask, "brick": [64, by, bz], "clusters": k},
-        "path_roofline": {"algorithmic_bytes": path_bytes, "achieved": round(path_bytes / (ms / 1e3) / 1e9, 1),
-                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": round(path_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "path_roofline": {"algorithmic_bytes": path_bytes, "achieved": round(path_gbs, 1),
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(path_gbs / HBM_PEAK_GBS, 4),
+                          "copy_ceiling": round(copy_gbs, 1) if copy_gbs else None,
+                          "frac_of_copy": round(path_gbs / copy_gbs, 4) if copy_gbs else None},
         "roofline": roofline,
         "kernels_ms": kernels,
+        "step_stats": step_stats,
     }
     del labels, sizes
     if not args.no_batched:
@@ -712,6 +800,10 @@ def main():
         torch.cuda.empty_cache()
         result["incremental"] = bench_incremental(hk, torch, phi, mask)
         log(f"incremental: {result['incremental']}")
+    if not args.no_configs:
+        torch.cuda.empty_cache()
+        result["configs"] = bench_configs(hk, torch)
+        log(f"configs: {result['configs']}")
     if not args.no_sweep:
         torch.cuda.empty_cache()
         result["cluster_sweep"] = bench_cluster_sweep(hk, torch, n=edge)
