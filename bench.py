@@ -498,6 +498,10 @@ def calibration_copy(torch, nbytes=1 << 30):
     del a, b
 
 
+TRACE_CMD_BATCHED = ("cd /tmp && TMPDIR=/tmp rocprofv3 --kernel-trace --stats -d <outdir> -o run -- "
+                     "python3 /root/repo/bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-served --no-classify "
+                     "--no-droplets --no-incremental --no-sweep --no-configs --no-profile")
+
 TRACE_CMD = ("cd /tmp && TMPDIR=/tmp rocprofv3 --kernel-trace --stats -d <outdir> -o run -- "
              "python3 /root/repo/bench.py --steps 5 --warmup 1 --no-cpu-baseline --no-batched --no-served")
 
@@ -510,6 +514,26 @@ def _kernel_name(full):
     return n.split("(")[0]
 
 
+def write_trace_summary(fname, title, part, cmd):
+    """profiles/<fname>: per-kernel calls and durations of the dispatches `part`."""
+    agg = {}
+    for n, s, e, gx, wx in part:
+        a = agg.setdefault((n, gx // wx), [])
+        a.append((e - s) / 1e3)
+    tot = sum(sum(v) for v in agg.values())
+    lines = [f"# {title}", "", "command (on an MI355X; the trace is split into the bench's sections by",
+             "dispatch order with `python bench.py --summarize-trace <outdir>/run_results.db`):", "",
+             f"    {cmd}", "",
+             f"{'kernel':<44} {'groups':>8} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}"]
+    for (n, groups), v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
+        lines.append(f"{n[:44]:<44} {groups:>8} {len(v):>6} {sum(v) / len(v):>10.1f} {min(v):>10.1f} "
+                     f"{max(v):>10.1f} {100 * sum(v) / tot:>6.1f}")
+    path = os.path.join(ROOT, "profiles", fname)
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(f"wrote {path}")
+
+
 def summarize_trace(db):
     """Split the kernel trace of TRACE_CMD (a rocprofv3 database) into its
     sections -- the 1024^3 labelling steps, the capsule decision, the droplet
@@ -520,6 +544,13 @@ def summarize_trace(db):
     con = sqlite3.connect(db)
     rows = con.execute("select name, start, end, grid_x, workgroup_x from kernels order by start").fetchall()
     ks = [(_kernel_name(n), s, e, gx, wx) for n, s, e, gx, wx in rows if "hk::" in n]
+    if any("::kb_" in k[0] for k in ks):
+        # a trace of TRACE_CMD_BATCHED: the grouped kernels of the 256-lattice stream
+        part = [k for k in ks if "::kb_" in k[0]]
+        write_trace_summary("kernel_trace_hk_label_batched_stream256.txt",
+                            "hk_label_batched kernel trace, the 256-lattice stream (config 5), grouped launches",
+                            part, TRACE_CMD_BATCHED)
+        return
     first = lambda pred: next(i for i, k in enumerate(ks) if pred(k[0]))
     last = lambda pred: max(i for i, k in enumerate(ks) if pred(k[0]))
     i_cls0 = first(lambda n: "k_local<1>" in n)          # the I == I0 labelling opens the decision
@@ -536,22 +567,7 @@ def summarize_trace(db):
          ks[i_cls1 + 1:i_ds1 + 1]),
     ]
     for fname, title, part in sections:
-        agg = {}
-        for n, s, e, gx, wx in part:
-            a = agg.setdefault((n, gx // wx), [])
-            a.append((e - s) / 1e3)
-        tot = sum(sum(v) for v in agg.values())
-        lines = [f"# {title}", "", "command (on an MI355X; the trace is split into the bench's sections by",
-                 "dispatch order with `python bench.py --summarize-trace <outdir>/run_results.db`):", "",
-                 f"    {TRACE_CMD}", "",
-                 f"{'kernel':<44} {'groups':>8} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}"]
-        for (n, groups), v in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
-            lines.append(f"{n[:44]:<44} {groups:>8} {len(v):>6} {sum(v) / len(v):>10.1f} {min(v):>10.1f} "
-                         f"{max(v):>10.1f} {100 * sum(v) / tot:>6.1f}")
-        path = os.path.join(ROOT, "profiles", fname)
-        with open(path, "w") as fh:
-            fh.write("\n".join(lines) + "\n")
-        print(f"wrote {path}")
+        write_trace_summary(fname, title, part, TRACE_CMD)
 
 
 def summarize_pmc(fetch_dir, write_dir, kernel, tag, calib_bytes=1 << 30):
