@@ -966,7 +966,7 @@ __device__ __forceinline__ void phase_merge(const Geo &g, int b, MergeLds &m) {
 // position is kept in its own array, written only by the node's thread.
 // --------------------------------------------------------------------------
 
-constexpr int HT_BITS = 11;
+constexpr int HT_BITS = 10;  // 1024 slots: 16 KB of LDS with the root words leaves eight workgroups per CU
 constexpr int HT = 1 << HT_BITS;  // hash slots: keys in hash[0, HT), sums in hash[HT, 2 HT)
 static_assert(2 * HT <= MAXRUNS, "the hash must fit in the run array of LdsBrick");
 
