@@ -691,7 +691,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build labels one lattice (or one batch) per GPU and "
+        print("bench.py measures one GPU only: the library labels one lattice (or one batch) per GPU and "
               "has no multi-GPU path; run it with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 

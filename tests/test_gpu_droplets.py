@@ -1,7 +1,9 @@
 """GPU parity of the droplet-size statistics (Sec. 5): hk_droplet_stats against
 the oracle -- histogram, count and summed size exactly; the sums of R, R^2,
-R^3 within the rounding of K terms of about one ulp each, summed in any
-order (relative 4 K eps, eps = 2^-52, derived in the design doc)."""
+R^3 within rounding.  Each term carries about one ulp from its cube root and
+powers, and a sum of K positive terms in any order adds at most K - 1 more
+roundings of about one ulp of the total, so 4 K eps relative (eps = 2^-52)
+bounds the difference between any two summation orders."""
 from __future__ import annotations
 
 import numpy as np
