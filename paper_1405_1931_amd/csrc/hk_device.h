@@ -39,6 +39,7 @@ constexpr int RMAX = WG / TPR;        // rows per brick at most (BY * BZ)
 constexpr int MAXRUNS = 32 * RMAX;    // a 64-bit row holds at most 32 runs
 constexpr int LPOS_BITS = RMAX <= 256 ? 14 : 15;  // bits of a brick-local site position row*64+x
 static_assert(RMAX <= 512, "run ids, positions and sizes are packed for at most 512 rows");
+static_assert(64 * RMAX <= (1 << 14), "brick sizes are accumulated as size << 16 in an int32");
 // the node phases (global union-find, node labels) are latency bound and
 // carry little work per brick: small workgroups keep many bricks in flight
 constexpr int WG_NODES = 256;
@@ -632,36 +633,33 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
     }
     __syncthreads();
 
-    // component sizes, accumulated in the root entry as -1 - size
+    // component sizes in one pass: every run subtracts len << 16 from its
+    // root's entry, so a root entry reads as its own index before the first
+    // subtraction and negative after it, while any other entry holds its
+    // root's index (non-negative, smaller than its own)
     {
         uint64_t m = mine;
         int id = first;
         while (m) {
             const int sb = __builtin_ctzll(m);
             m &= m - 1;
-            if (s.par[id] == id) s.par[id] = -1 - run_len(w, sb);
-            ++id;
-        }
-    }
-    __syncthreads();
-    {
-        uint64_t m = mine;
-        int id = first;
-        while (m) {
-            const int sb = __builtin_ctzll(m);
-            m &= m - 1;
-            const int p = s.par[id];
-            if (p >= 0) atomicAdd(&s.par[p], -run_len(w, sb));
+            const int v = s.par[id];
+            atomicAdd(&s.par[(v == id || v < 0) ? id : v], -(run_len(w, sb) << 16));
             ++id;
         }
     }
     __syncthreads();
 
-    // per slice: roots (high half) and boundary roots (low half), < 2^15 each
+    // per slice: roots (high half) and boundary roots (low half), < 2^15
+    // each; each root entry becomes -1 - size
     int c = 0;
     for (int j = 0; j < cnt; ++j) {
         const int id = first + j;
-        if (s.par[id] < 0) c += (1 << 16) + (bflag_get(s, id) ? 1 : 0);
+        const int v = s.par[id];
+        if (v < 0) {
+            s.par[id] = -1 - ((id - v) >> 16);
+            c += (1 << 16) + (bflag_get(s, id) ? 1 : 0);
+        }
     }
     int tot;
     const int pre = block_excl_scan(c, s.tmp, &tot);
