@@ -620,31 +620,27 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
     }
     jump_flatten(s, total);
 
-    // components touching a face shared with another brick (or a wrap)
-    if (live && w) {
-        const bool frow = (k.hyl && yl == 0) || (k.hyh && yl == k.ey - 1) || (k.hzl && zl == 0) ||
-                          (k.hzh && zl == k.ez - 1);
-        if (frow) {
-            for (int j = 0; j < cnt; ++j) bflag_set(s, s.par[first + j]);
-        } else if (q == 0) {
-            if (k.hxl && (w & 1ull)) bflag_set(s, s.par[offr]);
-            if (k.hxh && ((w >> (k.ex - 1)) & 1ull)) bflag_set(s, s.par[offr + __popcll(st) - 1]);
-        }
-    }
-    __syncthreads();
-
     // component sizes in one pass: every run subtracts len << 16 from its
     // root's entry, so a root entry reads as its own index before the first
     // subtraction and negative after it, while any other entry holds its
-    // root's index (non-negative, smaller than its own)
+    // root's index (non-negative, smaller than its own).  The same pass
+    // flags the components touching a face shared with another brick (or a
+    // wrap): every run of a y or z face row, the run at x = 0 and the last
+    // run of a row when it reaches the brick's last x.
     {
+        const bool frow = (k.hyl && yl == 0) || (k.hyh && yl == k.ey - 1) || (k.hzl && zl == 0) ||
+                          (k.hzh && zl == k.ez - 1);
+        const bool xl = k.hxl && (w & 1ull);
+        const bool xh = k.hxh && ((w >> (k.ex - 1)) & 1ull);
         uint64_t m = mine;
         int id = first;
         while (m) {
             const int sb = __builtin_ctzll(m);
             m &= m - 1;
             const int v = s.par[id];
-            atomicAdd(&s.par[(v == id || v < 0) ? id : v], -(run_len(w, sb) << 16));
+            const int r = (v == id || v < 0) ? id : v;
+            atomicAdd(&s.par[r], -(run_len(w, sb) << 16));
+            if (frow || (xl && sb == 0) || (xh && (st >> sb) == 1ull)) bflag_set(s, r);
             ++id;
         }
     }
