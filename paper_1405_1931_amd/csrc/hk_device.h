@@ -540,22 +540,22 @@ __device__ __forceinline__ void unite_rows(const Geo &g, LdsBrick &s, int rp, ui
     }
 }
 
-// pointer jumping: par[x] <- par[par[x]] over all runs until every entry is
-// a root; each entry is written only by its own thread, so concurrent reads
-// always see an ancestor
-__device__ __forceinline__ void jump_flatten(LdsBrick &s, int nruns) {
-    for (int round = 0; round < 64; ++round) {
-        int changed = 0;
-        for (int x = threadIdx.x; x < nruns; x += WG) {
-            const int p = lds_ld(s.par + x);
-            const int gp = lds_ld(s.par + p);
-            if (gp != p) {
-                lds_st(s.par + x, gp);
-                changed = 1;
-            }
+// every run's entry set to its root in one pass: each run walks up to its
+// root.  Every parent is an earlier run (links and unions point to the
+// smaller index), so a walk ends; the entries other threads write meanwhile
+// are roots of their runs, hence ancestors, and only shorten it.
+__device__ __forceinline__ void walk_flatten(LdsBrick &s, int nruns) {
+    for (int x = threadIdx.x; x < nruns; x += WG) {
+        const int p = lds_ld(s.par + x);
+        int r = p;
+        int gp = lds_ld(s.par + r);
+        for (int i = 0; gp != r && i < nruns; ++i) {  // at most x steps
+            r = gp;
+            gp = lds_ld(s.par + r);
         }
-        if (!__syncthreads_or(changed)) break;
+        if (r != p) lds_st(s.par + x, r);
     }
+    __syncthreads();
 }
 
 struct CoreOut {
@@ -618,7 +618,7 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
         }
         __syncthreads();
     }
-    jump_flatten(s, total);
+    walk_flatten(s, total);
 
     // component sizes in one pass: every run subtracts len << 16 from its
     // root's entry, so a root entry reads as its own index before the first
