@@ -564,6 +564,7 @@ struct CoreOut {
     int broots;  // components touching a shared face
     int cpre;    // components whose root run precedes this thread's slice
     int bpre;    // boundary components likewise
+    uint64_t rbits;  // start bits of this thread's root runs
 };
 
 __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsBrick &s) {
@@ -581,13 +582,11 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
         s.tmp[20] = 0;  // equivalence count
     }
     if (t < MAXRUNS / 32) s.bflag[t] = 0u;
+    for (int x = t; x < total; x += WG) s.par[x] = x;  // every run its own root
     __syncthreads();
     const int offr = live ? s.rowoff[row] : 0;
-    // runs of this slice: ids first .. first + count - 1
+    // id of the first run starting in this slice
     const int first = offr + __popcll(st & mask_lt(SLICE * q));
-    const int cnt = __popcll(mine);
-    for (int j = 0; j < cnt; ++j) s.par[first + j] = first + j;
-    __syncthreads();
 
     // rules 2/3 inside the brick against the row below (y-1) and the plane
     // below (z-1); runs of different rows only meet there
@@ -626,7 +625,9 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
     // root's index (non-negative, smaller than its own).  The same pass
     // flags the components touching a face shared with another brick (or a
     // wrap): every run of a y or z face row, the run at x = 0 and the last
-    // run of a row when it reaches the brick's last x.
+    // run of a row when it reaches the brick's last x.  The start bits of
+    // the slice's root runs are kept for the passes over roots only.
+    uint64_t rbits = 0;
     {
         const bool frow = (k.hyl && yl == 0) || (k.hyh && yl == k.ey - 1) || (k.hzl && zl == 0) ||
                           (k.hzh && zl == k.ez - 1);
@@ -639,6 +640,7 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
             m &= m - 1;
             const int v = s.par[id];
             const int r = (v == id || v < 0) ? id : v;
+            if (r == id) rbits |= 1ull << sb;
             atomicAdd(&s.par[r], -(run_len(w, sb) << 16));
             if (frow || (xl && sb == 0) || (xh && (st >> sb) == 1ull)) bflag_set(s, r);
             ++id;
@@ -649,13 +651,10 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
     // per slice: roots (high half) and boundary roots (low half), < 2^15
     // each; each root entry becomes -1 - size
     int c = 0;
-    for (int j = 0; j < cnt; ++j) {
-        const int id = first + j;
-        const int v = s.par[id];
-        if (v < 0) {
-            s.par[id] = -1 - ((id - v) >> 16);
-            c += (1 << 16) + (bflag_get(s, id) ? 1 : 0);
-        }
+    for (uint64_t m = rbits; m; m &= m - 1) {
+        const int id = offr + __popcll(st & ((1ull << __builtin_ctzll(m)) - 1ull));
+        s.par[id] = -1 - ((id - s.par[id]) >> 16);
+        c += (1 << 16) + (bflag_get(s, id) ? 1 : 0);
     }
     int tot;
     const int pre = block_excl_scan(c, s.tmp, &tot);
@@ -665,6 +664,7 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
     out.broots = tot & 0xFFFF;
     out.cpre = pre >> 16;
     out.bpre = pre & 0xFFFF;
+    out.rbits = rbits;
     return out;
 }
 
@@ -682,7 +682,7 @@ __device__ __forceinline__ int root_of(const LdsBrick &s, int run) {
 // After the brick's occupancy is in s.occ: label it, write its nodes,
 // interior components, run slots and face tables.
 __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b, LdsBrick &s) {
-    const int t = threadIdx.x, row = t / TPR, q = t % TPR;
+    const int t = threadIdx.x, row = t / TPR;
     const int R = g.R;
     if (t < R) s.rootw[t] = 0ull;
     __syncthreads();
@@ -711,8 +711,8 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
     if (row < R) {
         const uint64_t w = s.occ[row];
         const uint64_t st = run_starts(w);
-        uint64_t m = st & slice_bits(q);
-        int id = s.rowoff[row] + __popcll(st & mask_lt(SLICE * q));
+        uint64_t m = co.rbits;  // root runs only
+        const int offr = s.rowoff[row];
         int bi = co.bpre;
         int ii = co.cpre - co.bpre;
         const int yl = row & (g.BY - 1), zl = row >> g.lby;
@@ -720,8 +720,9 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
         while (m) {
             const int sb = __builtin_ctzll(m);
             m &= m - 1;
-            const int v = s.par[id];
-            if (v < 0) {
+            const int id = offr + __popcll(st & ((1ull << sb) - 1ull));
+            const int v = s.par[id];  // -1 - size
+            {
                 int c;
                 if (bflag_get(s, id)) {
                     c = bi++;
@@ -746,7 +747,6 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
                 }
                 s.par[id] = -1 - c;
             }
-            ++id;
         }
         if (rw) atomicOr((unsigned long long *)&s.rootw[row], (unsigned long long)rw);
     }
