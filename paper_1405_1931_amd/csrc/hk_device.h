@@ -168,6 +168,9 @@ __device__ __forceinline__ uint64_t run_starts(uint64_t w) { return w & ~(w << 1
 // bits 0..b inclusive
 __device__ __forceinline__ uint64_t mask_le(int b) { return b >= 63 ? ~0ull : ((2ull << b) - 1ull); }
 
+// set bits of x at positions 0..b, for 0 <= b <= 63 (one shift, no mask)
+__device__ __forceinline__ int pop_le(uint64_t x, int b) { return __popcll(x << (63 - b)); }
+
 // bits 0..b-1
 __device__ __forceinline__ uint64_t mask_lt(int b) { return b <= 0 ? 0ull : (b >= 64 ? ~0ull : ((1ull << b) - 1ull)); }
 
@@ -515,9 +518,8 @@ __device__ __forceinline__ void link_rows(LdsBrick &s, int rp, uint64_t w, uint6
     while (seg) {
         const int bb = __builtin_ctzll(seg);
         seg &= seg - 1;
-        const uint64_t mk = mask_le(bb);
-        const int a = offr + __popcll(st & mk) - 1;
-        const int c = offp + __popcll(stp & mk) - 1;
+        const int a = offr + pop_le(st, bb) - 1;
+        const int c = offp + pop_le(stp, bb) - 1;
         if (atomicCAS(s.par + a, a, c) != a) {
             const int e = atomicAdd(&s.tmp[20], 1);
             if (nruns + e < MAXRUNS) s.par[nruns + e] = (a << 16) | c;
@@ -535,8 +537,7 @@ __device__ __forceinline__ void unite_rows(const Geo &g, LdsBrick &s, int rp, ui
     while (seg) {
         const int bb = __builtin_ctzll(seg);
         seg &= seg - 1;
-        const uint64_t mk = mask_le(bb);
-        l_unite(g, s.par, offr + __popcll(st & mk) - 1, offp + __popcll(stp & mk) - 1);
+        l_unite(g, s.par, offr + pop_le(st, bb) - 1, offp + pop_le(stp, bb) - 1);
     }
 }
 
@@ -652,7 +653,7 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
     // each; each root entry becomes -1 - size
     int c = 0;
     for (uint64_t m = rbits; m; m &= m - 1) {
-        const int id = offr + __popcll(st & ((1ull << __builtin_ctzll(m)) - 1ull));
+        const int id = offr + pop_le(st, __builtin_ctzll(m)) - 1;
         s.par[id] = -1 - ((id - s.par[id]) >> 16);
         c += (1 << 16) + (bflag_get(s, id) ? 1 : 0);
     }
@@ -720,7 +721,7 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
         while (m) {
             const int sb = __builtin_ctzll(m);
             m &= m - 1;
-            const int id = offr + __popcll(st & ((1ull << sb) - 1ull));
+            const int id = offr + pop_le(st, sb) - 1;
             const int v = s.par[id];  // -1 - size
             {
                 int c;
@@ -786,7 +787,7 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
         const uint64_t w = wave_uniform64(s.occ[r]);
         uint16_t e = NOSITE;
         if ((w >> lane) & 1ull) {
-            const int run = wave_uniform(s.rowoff[r]) + (int)__popcll(run_starts(w) & mask_le(lane)) - 1;
+            const int run = wave_uniform(s.rowoff[r]) + pop_le(run_starts(w), lane) - 1;
             const int bidx = -1 - s.par[root_of(s, run)];
             if (bidx >= 0 && bidx < g.cap)
                 e = (uint16_t)bidx;
