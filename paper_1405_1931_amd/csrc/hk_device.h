@@ -763,8 +763,16 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
     }
 
     // component slot of every run, for the final pass
-    uint16_t *L = g.runlab + (int64_t)b * g.runcap;
-    for (int id = t; id < co.nruns && id < g.runcap; id += WG) L[id] = (uint16_t)(-1 - s.par[root_of(s, id)]);
+    {
+        // two slots per 32-bit store (runcap is a multiple of four)
+        uint32_t *L2 = reinterpret_cast<uint32_t *>(g.runlab + (int64_t)b * g.runcap);
+        const int nr = min(co.nruns, g.runcap);
+        for (int i = t; 2 * i < nr; i += WG) {
+            const uint32_t lo = (uint16_t)(-1 - s.par[root_of(s, 2 * i)]);
+            const uint32_t hi = 2 * i + 1 < nr ? (uint16_t)(-1 - s.par[root_of(s, 2 * i + 1)]) : 0u;
+            L2[i] = lo | (hi << 16);
+        }
+    }
 
     uint16_t *F = g.face + (int64_t)b * g.fstride;
     // y and z face rows, spread over the waves: entry f < ez is row (0, f)
