@@ -1,0 +1,75 @@
+"""The brick labelling when a brick's runs and its stored rule-3 equivalences
+(Sec. 2) together exceed the brick's run table: the overlaps are then united
+again directly, row against row.
+
+Planes of even x, fully occupied, give every 64 x 16 x 16 brick 32
+single-site runs in each of its 256 rows (8192 runs: the whole table) and
+an equivalence for almost every run (its parent through y - 1, a second
+link through z - 1), so every brick takes that path.  With nx even the
+planes never touch, also across an x wrap (x = nx - 1 is odd): K = nx / 2,
+every size ny * nz, plane x numbered x / 2 + 1.  Ragged lattices, odd nx
+under a wrap and stripes with noise are checked against the oracle."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def hk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1405_1931_amd as hk
+
+    hk.set_brick(16, 16)  # the brick whose run table the stripes fill
+    yield hk
+    hk.set_brick(0, 0)
+
+
+def stripes_np(shape, noise=0.0, seed=0):
+    nz, ny, nx = shape
+    occ = np.broadcast_to((np.arange(nx) % 2 == 0).reshape(1, 1, -1), shape)
+    if noise:
+        occ = occ | (np.random.default_rng(seed).random(shape) < noise)
+    return np.where(occ, 1.0, -1.0).astype(np.float32)
+
+
+@pytest.mark.parametrize("mask", [0, 7])
+def test_stripes_closed_form(hk, mask):
+    for shape in ((64, 64, 256), (128, 96, 1024)):
+        print(f"[overflow] x stripes {shape} mask {mask}", flush=True)
+        nz, ny, nx = shape
+        x = torch.arange(nx, device="cuda", dtype=torch.int32).view(1, 1, nx)
+        occ = (x % 2) == 0
+        phi = torch.where(occ, 1.0, -1.0).to(torch.float32).expand(nz, ny, nx).contiguous()
+        labels, k, sizes = hk.label(phi, mask)
+        assert k == nx // 2
+        assert bool((sizes == ny * nz).all())
+        expect = torch.where(occ, torch.div(x, 2, rounding_mode="floor") + 1, 0).to(torch.int32)
+        assert torch.equal(labels, expect.expand(nz, ny, nx))
+        assert hk.device_error() == 0
+
+
+def assert_oracle(hk, phi_np, mask, what):
+    print(f"[overflow] {what} shape={phi_np.shape} mask={mask}", flush=True)
+    lab, k, s = hk.label(torch.from_numpy(phi_np).cuda(), mask)
+    exp = oracle.label(phi_np, mask)
+    assert k == exp[1], what
+    assert np.array_equal(lab.cpu().numpy(), exp[0]), what
+    assert np.array_equal(s.cpu().numpy(), exp[2]), what
+    assert hk.device_error() == 0
+
+
+@pytest.mark.parametrize("shape", [(40, 24, 130), (17, 33, 199), (32, 32, 128)])
+def test_stripes_vs_oracle(hk, shape):
+    for mask in (0, 1, 6, 7):
+        assert_oracle(hk, stripes_np(shape), mask, "x stripes")
+    for noise, seed in ((0.02, 1), (0.1, 2)):
+        for mask in (0, 7):
+            assert_oracle(hk, stripes_np(shape, noise, seed), mask, f"x stripes + {noise} noise")

@@ -129,6 +129,35 @@ def test_site_checkerboard(shape, oracle_lib):
         assert k7 == n // 2 and np.array_equal(lab7, expect)
 
 
+def x_stripes(shape):
+    """Occupied iff x is even: full planes x = 0, 2, 4, ..."""
+    x = np.arange(shape[2]).reshape(1, 1, -1)
+    return np.broadcast_to(np.where(x % 2 == 0, 1.0, -1.0), shape).astype(np.float32).copy()
+
+
+@pytest.mark.parametrize("mask", ALL_MASKS)
+@pytest.mark.parametrize("shape", [(5, 6, 16), (3, 4, 9), (1, 1, 7), (2, 3, 2)])
+def test_x_stripes(shape, mask, oracle_lib):
+    """Planes of even x: each is one cluster, numbered by x (its lowest site
+    (x, 0, 0) precedes the next plane's).  With x periodic and nx odd, plane
+    nx - 1 (even) wraps onto plane 0 and joins cluster 1."""
+    nz, ny, nx = shape
+    lab, k, s = oracle.label(x_stripes(shape), mask, lib=oracle_lib)
+    planes = (nx + 1) // 2
+    wrap = bool(mask & 1) and nx % 2 == 1 and nx > 1
+    expect_k = planes - 1 if wrap else planes
+    assert k == expect_k
+    x = np.arange(nx)
+    per_x = np.where(x % 2 == 0, x // 2 + 1, 0)
+    if wrap:
+        per_x[nx - 1] = 1
+    assert np.array_equal(lab, np.broadcast_to(per_x.reshape(1, 1, -1), shape))
+    expect_s = [ny * nz] * expect_k
+    if wrap:
+        expect_s[0] = 2 * ny * nz
+    assert list(s) == expect_s
+
+
 @pytest.mark.parametrize("b", [1, 2, 4, 8])
 @pytest.mark.parametrize("mask", [0, 7])
 def test_block_checkerboard(b, mask, oracle_lib):
