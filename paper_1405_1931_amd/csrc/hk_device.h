@@ -554,7 +554,7 @@ __device__ __forceinline__ void walk_flatten(LdsBrick &s, int nruns) {
             r = gp;
             gp = lds_ld(s.par + r);
         }
-        if (r != p) lds_st(s.par + x, r);
+        lds_st(s.par + x, r);
     }
     __syncthreads();
 }
@@ -632,8 +632,10 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
     {
         const bool frow = (k.hyl && yl == 0) || (k.hyh && yl == k.ey - 1) || (k.hzl && zl == 0) ||
                           (k.hzh && zl == k.ez - 1);
-        const bool xl = k.hxl && (w & 1ull);
-        const bool xh = k.hxh && ((w >> (k.ex - 1)) & 1ull);
+        // x-face runs by id: the row's first run when it starts at x = 0, its
+        // last when it reaches the brick's last x (-1: none)
+        const int xlo = k.hxl && (w & 1ull) ? offr : -1;
+        const int xhi = k.hxh && ((w >> (k.ex - 1)) & 1ull) ? offr + __popcll(st) - 1 : -1;
         uint64_t m = mine;
         int id = first;
         while (m) {
@@ -643,7 +645,7 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
             const int r = (v == id || v < 0) ? id : v;
             if (r == id) rbits |= 1ull << sb;
             atomicAdd(&s.par[r], -(run_len(w, sb) << 16));
-            if (frow || (xl && sb == 0) || (xh && (st >> sb) == 1ull)) bflag_set(s, r);
+            if (frow || id == xlo || id == xhi) bflag_set(s, r);
             ++id;
         }
     }
