@@ -73,3 +73,18 @@ def test_stripes_vs_oracle(hk, shape):
     for noise, seed in ((0.02, 1), (0.1, 2)):
         for mask in (0, 7):
             assert_oracle(hk, stripes_np(shape, noise, seed), mask, f"x stripes + {noise} noise")
+
+
+def test_stripes_batched(hk):
+    """The same path in the grouped launches of one batched call."""
+    shapes = [(40, 24, 130), (32, 32, 128), (17, 33, 199), (64, 64, 256)]
+    items = [(stripes_np(sh, 0.05 * (i % 2), seed=i), (0, 7, 1, 6)[i]) for i, sh in enumerate(shapes)]
+    print(f"[overflow] batched x stripes, {len(items)} jobs", flush=True)
+    out = hk.label_batched([(torch.from_numpy(p).cuda(), m) for p, m in items])
+    torch.cuda.synchronize()
+    assert hk.device_error() == 0
+    for j, ((p, m), (lab, k, sz)) in enumerate(zip(items, out)):
+        exp = oracle.label(p, m)
+        assert k == exp[1], f"job {j}"
+        assert np.array_equal(lab.cpu().numpy(), exp[0]), f"job {j}"
+        assert np.array_equal(sz.cpu().numpy(), exp[2]), f"job {j}"
