@@ -88,3 +88,28 @@ def test_stripes_batched(hk):
         assert k == exp[1], f"job {j}"
         assert np.array_equal(lab.cpu().numpy(), exp[0]), f"job {j}"
         assert np.array_equal(sz.cpu().numpy(), exp[2]), f"job {j}"
+
+
+@pytest.mark.parametrize("mask", [0, 7])
+def test_stripes_incremental(hk, mask):
+    """The same path for the bricks an incremental call labels anew: every
+    call equals the oracle, and only the bricks whose words changed are
+    labelled again."""
+    shape = (48, 40, 192)  # 3 x 3 x 3 bricks: full along x and z, ragged along y
+    nz, ny, nx = shape
+    f0 = stripes_np(shape)
+    f1 = f0.copy()
+    f1[20, 20, 71] = 1.0    # joins planes 70 and 72 inside brick (1, 1, 1)
+    f2 = f1.copy()
+    f2[0, 0, 1:4] = 1.0     # joins planes 0, 2 and 4 in brick (0, 0, 0)
+    with hk.Incremental(shape, mask) as st:
+        for f, what, rel in ((f0, "stripes", 27), (f1, "one site joins two planes", 1),
+                             (f2, "a short run joins three planes", 1), (f2, "unchanged", 0)):
+            print(f"[overflow] incremental {what} mask {mask}", flush=True)
+            labels, k, sizes, r = st.label(torch.from_numpy(f).cuda())
+            el, ek, es = oracle.label(f, mask)
+            assert k == ek, what
+            assert np.array_equal(labels.cpu().numpy(), el), what
+            assert np.array_equal(sizes.cpu().numpy(), es[:ek]), what
+            assert r == rel, (what, r)
+            assert st.device_error() == 0
