@@ -81,7 +81,7 @@ void choose_brick(int nx, int ny, int nz, bool batch, int *by, int *bz) {
 
 struct Layout {
     int64_t occ, root, wpre, face, bcount, npar, nkey, nsize, nlpos, nrootpos, runlab, icomp, icount, nrun,
-        rowcnt, blksum, total;
+        slab, rowo, rowcnt, blksum, total;
 };
 
 // geometry (no pointers) of one lattice; false if it cannot be handled
@@ -112,7 +112,7 @@ bool make_geo(int nx, int ny, int nz, uint32_t mask, int by, int bz, Geo *g) {
     g->runcap = (g->R * ((exm + 1) / 2) + 3) & ~3;
     g->icap = (int)c2;                   // components of a brick <= half its sites
     if (nb * (int64_t)g->runcap > ((int64_t)1 << 40) || nb * (int64_t)g->icap > ((int64_t)1 << 40)) return false;
-    g->fstride = 2 * g->R + 128 * bz + 128 * by;
+    g->fstride = 2 * g->R;
     g->rows = ny * nz;
     g->nblk = (g->rows + WG - 1) / WG;
     return true;
@@ -142,6 +142,8 @@ Layout layout_of(const Geo &g, int64_t base) {
     L.icomp = take((int64_t)g.nb * g.icap * 4);
     L.icount = take((int64_t)g.nb * 4);
     L.nrun = take((int64_t)g.nb * 4);
+    L.slab = take(nodes * 4);
+    L.rowo = take(words * 2);
     L.rowcnt = take((int64_t)g.rows * 4);
     L.blksum = take((int64_t)g.nblk * 4);
     L.total = o - base;
@@ -163,6 +165,8 @@ void bind(Geo *g, char *base, const Layout &L) {
     g->icomp = (uint32_t *)(base + L.icomp);
     g->icount = (int32_t *)(base + L.icount);
     g->nrun = (int32_t *)(base + L.nrun);
+    g->slab = (int32_t *)(base + L.slab);
+    g->rowo = (uint16_t *)(base + L.rowo);
     g->rowcnt = (int32_t *)(base + L.rowcnt);
     g->blksum = (int32_t *)(base + L.blksum);
 }

@@ -73,10 +73,16 @@ __global__ __launch_bounds__(WG) void kb_rowpre(GroupView v) {
 }
 
 
+__global__ __launch_bounds__(WG_RANK) __attribute__((amdgpu_waves_per_eu(8))) void kb_rank(GroupView v) {
+    int i;
+    const Geo &g = locate(v, 6, blockIdx.x, &i);
+    phase_rank(g, i);
+}
+
 __global__ __launch_bounds__(WG) void kb_write(GroupView v) {
     __shared__ LdsBrick s;
     int i;
-    const Geo &g = locate(v, 6, blockIdx.x, &i);
+    const Geo &g = locate(v, 7, blockIdx.x, &i);
     phase_write(g, i, s);
 }
 
@@ -218,7 +224,7 @@ void release_batched() {
     g_arena = CaptureArena();
 }
 
-// Enqueue the table upload and the seven grouped kernels of a validated
+// Enqueue the table upload and the eight grouped kernels of a validated
 // batch; `ws` holds at least the bytes validate_and_plan reported.  The
 // caller holds the workspace mutex (it guards the staging ring).
 int enqueue_batched(const hk_job *jobs, int n_jobs, const std::vector<Geo> &geos, char *ws, int32_t *err,
@@ -267,7 +273,8 @@ int enqueue_batched(const hk_job *jobs, int n_jobs, const std::vector<Geo> &geos
     hipLaunchKernelGGL(kb_rowsum, dim3((unsigned)items[3]), blk, 0, stream, v);
     hipLaunchKernelGGL(kb_scanblk, dim3((unsigned)items[4]), blk, 0, stream, v);
     hipLaunchKernelGGL(kb_rowpre, dim3((unsigned)items[5]), blk, 0, stream, v);
-    hipLaunchKernelGGL(kb_write, dim3((unsigned)items[6]), blk, 0, stream, v);
+    hipLaunchKernelGGL(kb_rank, dim3((unsigned)items[6]), dim3(WG_RANK), 0, stream, v);
+    hipLaunchKernelGGL(kb_write, dim3((unsigned)items[7]), blk, 0, stream, v);
     return hipGetLastError() == hipSuccess ? HK_OK : HK_ERR_HIP;
 }
 

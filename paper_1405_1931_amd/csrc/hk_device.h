@@ -60,7 +60,7 @@ struct Geo {
     int32_t BY, BZ, lby, lbz, R;
     int32_t nbx, nby, nbz, nb;
     int32_t cap;      // node slots per brick
-    int32_t fstride;  // face-table entries per brick
+    int32_t fstride;  // x-face table entries per brick (2 R)
     int32_t rows;     // ny * nz lattice rows
     int32_t nblk;     // ceil(rows / WG)
     // caller buffers
@@ -73,7 +73,7 @@ struct Geo {
     uint64_t *occ;    // [nb][R] occupancy words, brick-major
     uint64_t *root;   // [nb][R] bit set at the lowest site of every cluster
     int32_t *wpre;    // [nb][R] #cluster roots before this word, linear order
-    uint16_t *face;   // [nb][fstride] node slot of each face site
+    uint16_t *face;   // [nb][fstride] node slot at each x-face site of each row
     int32_t *bcount;  // [nb] nodes used by each brick
     int32_t *npar;    // [nb*cap] node parent
     int32_t *nkey;    // [nb*cap] linear index of the node's lowest site
@@ -86,6 +86,8 @@ struct Geo {
     int32_t *icount;  // [nb] interior components of each brick
     int32_t runcap;   // run slots per brick
     int32_t icap;     // interior component slots per brick
+    int32_t *slab;    // [nb*cap] final label of each node's cluster
+    uint16_t *rowo;   // [nb][R] id of the first run of each brick row
     int32_t *rowcnt;  // [rows] roots per lattice row
     int32_t *blksum;  // [nblk] roots per block of rows, then their prefix
     int32_t *err;     // sticky check flag
@@ -198,6 +200,14 @@ __device__ __forceinline__ void gl_st(int32_t *p, int v) {
 // is the same across a wave, and per-row arithmetic left in vector registers
 // costs a full wave instruction each.
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// the value of lane j (a constant or wave-uniform index), whatever the
+// execution mask; the result is wave-uniform
+__device__ __forceinline__ int lane_value(int v, int j) { return __builtin_amdgcn_readlane(v, j); }
+__device__ __forceinline__ uint64_t lane_value64(uint64_t v, int j) {
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, j);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), j);
+    return ((uint64_t)hi << 32) | lo;
+}
 __device__ __forceinline__ uint64_t wave_uniform64(uint64_t v) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
@@ -258,13 +268,11 @@ __device__ __forceinline__ Brick brick_of(const Geo &g, int b) {
     return k;
 }
 
-// face-table sections of one brick
+// x-face table sections of one brick: the slot of the first run of each row
+// (when it starts at x = 0), then of the last run (when it ends at the
+// brick's last x)
 __device__ __forceinline__ int f_xlo(const Geo &) { return 0; }
 __device__ __forceinline__ int f_xhi(const Geo &g) { return g.R; }
-__device__ __forceinline__ int f_ylo(const Geo &g) { return 2 * g.R; }
-__device__ __forceinline__ int f_yhi(const Geo &g) { return 2 * g.R + 64 * g.BZ; }
-__device__ __forceinline__ int f_zlo(const Geo &g) { return 2 * g.R + 128 * g.BZ; }
-__device__ __forceinline__ int f_zhi(const Geo &g) { return 2 * g.R + 128 * g.BZ + 64 * g.BY; }
 
 // --------------------------------------------------------------------------
 // union-find inside LDS (runs of one brick): link toward the smaller run id,
@@ -760,6 +768,7 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
     }
     __syncthreads();
     if (t < R) {
+        g.rowo[(int64_t)b * R + t] = (uint16_t)s.rowoff[t];
         g.root[(int64_t)b * R + t] = s.rootw[t];
         if (g.incr != 0) g.rootw0[(int64_t)b * R + t] = s.rootw[t];
     }
@@ -776,36 +785,9 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
         }
     }
 
+    // x-face tables (the y and z faces are found from the words, run offsets
+    // and run slots by the merge phase)
     uint16_t *F = g.face + (int64_t)b * g.fstride;
-    // y and z face rows, spread over the waves: entry f < ez is row (0, f)
-    // of the low y face, then the high y face, the low z face, the high z face
-    const int lane = t & 63, wv = wave_uniform(t >> 6);
-    for (int f = wv; f < 2 * (k.ey + k.ez); f += NW) {
-        int yl, zl, sec;
-        bool on;
-        if (f < k.ez) {
-            yl = 0, zl = f, sec = f_ylo(g) + zl * 64, on = k.hyl;
-        } else if (f < 2 * k.ez) {
-            yl = k.ey - 1, zl = f - k.ez, sec = f_yhi(g) + zl * 64, on = k.hyh;
-        } else if (f < 2 * k.ez + k.ey) {
-            yl = f - 2 * k.ez, zl = 0, sec = f_zlo(g) + yl * 64, on = k.hzl;
-        } else {
-            yl = f - 2 * k.ez - k.ey, zl = k.ez - 1, sec = f_zhi(g) + yl * 64, on = k.hzh;
-        }
-        if (!on) continue;
-        const int r = yl + g.BY * zl;
-        const uint64_t w = wave_uniform64(s.occ[r]);
-        uint16_t e = NOSITE;
-        if ((w >> lane) & 1ull) {
-            const int run = wave_uniform(s.rowoff[r]) + pop_le(run_starts(w), lane) - 1;
-            const int bidx = -1 - s.par[root_of(s, run)];
-            if (bidx >= 0 && bidx < g.cap)
-                e = (uint16_t)bidx;
-            else
-                set_err(g, ERR_FACE);
-        }
-        F[sec + lane] = e;
-    }
     if (t < R) {
         const int yl = t & (g.BY - 1), zl = t >> g.lby;
         if (yl < k.ey && zl < k.ez) {
@@ -839,25 +821,40 @@ __device__ __forceinline__ void phase_local(const Geo &g, int b, LdsBrick &s) {
 
 
 // --------------------------------------------------------------------------
-// phase: merge -- unite nodes across the brick's low x/y/z faces (the high
-// faces are the low faces of the next bricks; wraps pair brick 0 with the
-// last brick of a periodic axis).
+// phase: merge -- unite the nodes that meet across the brick's low x, y and
+// z faces (the high faces are the low faces of the next bricks; wraps pair
+// the first and the last brick of a periodic axis).
 //
-// The three low faces are cut into chunks of 64 consecutive face sites (one
-// x row of a y or z face, or 64 rows of the x face), one site per lane, so
-// the check "the previous site along the face already joined the same two
-// components" is a shuffle.  The waves read their chunks' face entries
-// several chunks at a time and append the pairs to unite to an LDS list; the
-// unions are then spread evenly over the workgroup.
+// x face: the x-face tables hold the slot of each row's first run (when it
+// starts at x = 0) and last run (when it ends at the brick's last x); one
+// row per lane.  A row whose predecessor in the same plane (y - 1) also has
+// both face sites occupied is skipped: the two sites on each side are
+// face-adjacent, so that row already joined the same two components.
+// y and z faces: the face row of this brick and the face row across it are
+// whole brick rows.  Their common occupied sites form segments, and each
+// segment joins exactly one run of each row; the runs' slots come from the
+// run tables at the rows' first-run offsets.  One face row per wave, one
+// site per lane: the lane at a segment start looks up the two slots and
+// drops its pair when the previous segment of the row had the same one.
+// The pairs are collected in LDS and then united, spread evenly over the
+// workgroup.
 // --------------------------------------------------------------------------
 
 constexpr int MERGE_CAP = 1024;  // pairs held in LDS; further pairs are united where found
-constexpr int MERGE_U = 3;       // chunks per wave read together
+constexpr int MERGE_F = 8;       // y/z face rows a wave takes at a time
 
 struct MergeLds {
     int2 pair[MERGE_CAP];
     int count;
 };
+
+__device__ __forceinline__ void merge_push(const Geo &g, MergeLds &m, int na, int nc) {
+    const int i = atomicAdd(&m.count, 1);
+    if (i < MERGE_CAP)
+        m.pair[i] = make_int2(na, nc);
+    else
+        g_unite(g, na, nc);
+}
 
 __device__ __forceinline__ void phase_merge(const Geo &g, int b, MergeLds &m) {
     const Brick k = brick_of(g, b);
@@ -865,92 +862,121 @@ __device__ __forceinline__ void phase_merge(const Geo &g, int b, MergeLds &m) {
     const int wv = wave_uniform(threadIdx.x >> 6), nw = blockDim.x >> 6;
     if (threadIdx.x == 0) m.count = 0;
     __syncthreads();
-    const uint16_t *F = g.face + (int64_t)b * g.fstride;
     const int bxn = k.bx > 0 ? b - 1 : b + (g.nbx - 1);
     const int byn = k.by > 0 ? b - g.nbx : b + (g.nby - 1) * g.nbx;
     const int bzn = k.bz > 0 ? b - g.nbx * g.nby : b + (g.nbz - 1) * g.nbx * g.nby;
-    const int cx = k.hxl ? (g.R + 63) >> 6 : 0, cy = k.hyl ? g.BZ : 0, cz = k.hzl ? g.BY : 0;
-    const int nch = cx + cy + cz;
-    // each wave takes a contiguous run of chunks, so that on the y and z
-    // faces (one chunk per face row) a lane sees the site one row back and
-    // can drop a pair identical to the one recorded there: a cluster that
-    // crosses a face meets the same two components row after row
-    const int per = (nch + nw - 1) / nw;
-    const int cbeg = wv * per, cend = min(nch, cbeg + per);
-    uint16_t pa = NOSITE, pc = NOSITE;  // this lane's pair one face row back
-    for (int c0 = cbeg; c0 < cend; c0 += MERGE_U) {
-        uint16_t fa[MERGE_U], fc[MERGE_U];
-        bool pre[MERGE_U];
-        int nbb[MERGE_U];
-#pragma unroll
-        for (int u = 0; u < MERGE_U; ++u) {
-            const int c = c0 + u;  // wave-uniform
-            fa[u] = fc[u] = NOSITE;
-            pre[u] = false;
-            nbb[u] = b;
-            if (c >= cend) continue;
-            const uint16_t *Fs, *Gs;
-            int e;
-            bool valid;
-            if (c < cx) {  // x face: entry = brick row
-                e = c * 64 + lane;
-                const int yl = e & (g.BY - 1), zl = e >> g.lby;
-                valid = e < g.R && yl < k.ey && zl < k.ez;
-                nbb[u] = bxn;
-                Fs = F + f_xlo(g);
-                Gs = g.face + (int64_t)bxn * g.fstride + f_xhi(g);
-                // row e-1 (same plane) is in lane-1, except at lane 0 of a
-                // chunk that starts inside a y row (BY > 64)
-                pre[u] = valid && yl > 0 && lane == 0;
-            } else if (c < cx + cy) {  // low y face: entry = zl * 64 + x
-                const int zl = c - cx;
-                e = zl * 64 + lane;
-                valid = zl < k.ez && lane < k.ex;
-                nbb[u] = byn;
-                Fs = F + f_ylo(g);
-                Gs = g.face + (int64_t)byn * g.fstride + f_yhi(g);
-            } else {  // low z face: entry = yl * 64 + x
-                const int yl = c - cx - cy;
-                e = yl * 64 + lane;
-                valid = yl < k.ey && lane < k.ex;
-                nbb[u] = bzn;
-                Fs = F + f_zlo(g);
-                Gs = g.face + (int64_t)bzn * g.fstride + f_zhi(g);
-            }
+
+    if (k.hxl) {
+        const uint16_t *Fs = g.face + (int64_t)b * g.fstride + f_xlo(g);
+        const uint16_t *Gs = g.face + (int64_t)bxn * g.fstride + f_xhi(g);
+        for (int e0 = 64 * wv; e0 < g.R; e0 += 64 * nw) {
+            const int e = e0 + lane;
+            const int yl = e & (g.BY - 1), zl = e >> g.lby;
+            const bool valid = e < g.R && yl < k.ey && zl < k.ez;
+            uint16_t fa = NOSITE, fc = NOSITE;
             if (valid) {
-                fa[u] = Fs[e];
-                fc[u] = Gs[e];
-                if (pre[u]) pre[u] = Fs[e - 1] != NOSITE && Gs[e - 1] != NOSITE;
+                fa = Fs[e];
+                fc = Gs[e];
+            }
+            const bool both = fa != NOSITE && fc != NOSITE;
+            // row e - 1 (same plane when yl > 0) is in lane - 1, except at
+            // lane 0 of a chunk that starts inside a y row (BY > 64)
+            bool prev = __shfl_up((int)both, 1, 64) != 0;
+            if (lane == 0) prev = valid && yl > 0 && Fs[e - 1] != NOSITE && Gs[e - 1] != NOSITE;
+            if (both && !(yl > 0 && prev)) {
+                if (fa < g.cap && fc < g.cap)
+                    merge_push(g, m, b * g.cap + fa, bxn * g.cap + fc);
+                else
+                    set_err(g, ERR_FACE);
             }
         }
+    }
+
+    // extents of the neighbours across the low y and z faces (a wrap pairs
+    // the brick with the last brick of the axis, which may be partial)
+    const int eyn = k.by > 0 ? g.BY : g.ny - (g.nby - 1) * g.BY;
+    const int ezn = k.bz > 0 ? g.BZ : g.nz - (g.nbz - 1) * g.BZ;
+    const int cy = k.hyl ? k.ez : 0, cz = k.hzl ? k.ey : 0;
+    const uint64_t le = mask_le(lane), lt = mask_lt(lane);
+    // Each wave takes MERGE_F consecutive face rows at a time: lane j loads
+    // the words and first-run offsets of face row j (one round trip), then
+    // the run slots of every segment start of the MERGE_F rows are requested
+    // together (a second round trip).  Consecutive face rows of one face are
+    // neighbours across the face's other axis, so a lane at a segment start
+    // drops its pair when the same site of the face row before had the same
+    // pair (a cluster that crosses a face meets the same two components row
+    // after row).
+    for (int f0 = MERGE_F * wv; f0 < cy + cz; f0 += MERGE_F * nw) {
+        uint64_t lwa = 0, lwb = 0;
+        int loa = 0, lob = 0;
+        {
+            const int f = f0 + lane;
+            if (lane < MERGE_F && f < cy + cz) {
+                int ra, rb, bn;
+                if (f < cy) {
+                    bn = byn;
+                    ra = g.BY * f;
+                    rb = (eyn - 1) + g.BY * f;
+                } else {
+                    bn = bzn;
+                    ra = f - cy;
+                    rb = (f - cy) + g.BY * (ezn - 1);
+                }
+                lwa = g.occ[(int64_t)b * g.R + ra];
+                lwb = g.occ[(int64_t)bn * g.R + rb];
+                loa = g.rowo[(int64_t)b * g.R + ra];
+                lob = g.rowo[(int64_t)bn * g.R + rb];
+            }
+        }
+        int sa[MERGE_F], sb[MERGE_F];
+        uint64_t sgj[MERGE_F];
 #pragma unroll
-        for (int u = 0; u < MERGE_U; ++u) {
-            const int c = c0 + u;
-            if (c >= cend) continue;
-            const bool both = fa[u] != NOSITE && fc[u] != NOSITE;
-            // was the previous site along the face a pair too?
-            const int up = __shfl_up((int)both, 1, 64);
-            bool prev;
-            if (c < cx) {
-                const int e = c * 64 + lane;
-                prev = lane > 0 ? (up != 0 && (e & (g.BY - 1)) > 0) : pre[u];
-            } else {
-                prev = lane > 0 && up != 0;
+        for (int j = 0; j < MERGE_F; ++j) {
+            const uint64_t wa = lane_value64(lwa, j);
+            const uint64_t wb = lane_value64(lwb, j);
+            const int oa = lane_value(loa, j), ob = lane_value(lob, j);
+            const uint64_t o = wa & wb;
+            sgj[j] = o & ~(o << 1);  // segment starts
+            sa[j] = sb[j] = -1;
+            if ((sgj[j] >> lane) & 1ull) {
+                const int f = f0 + j;
+                const int bn = f < cy ? byn : bzn;
+                const int ia = oa + __popcll(run_starts(wa) & le) - 1;
+                const int ib = ob + __popcll(run_starts(wb) & le) - 1;
+                sa[j] = g.runlab[(int64_t)b * g.runcap + min(ia, g.runcap - 1)];
+                sb[j] = g.runlab[(int64_t)bn * g.runcap + min(ib, g.runcap - 1)];
             }
-            // the previous chunk of this wave is the face row just before (a
-            // chunk of the same y or z face), or the pair carried is NOSITE
-            const bool first_row = c == cx || c == cx + cy;
-            const bool vert = c > cx && !first_row && c > cbeg && fa[u] == pa && fc[u] == pc;
-            pa = fa[u];
-            pc = fc[u];
-            if (both && !prev && !vert) {
-                const int na = b * g.cap + fa[u], nc = nbb[u] * g.cap + fc[u];
-                const int i = atomicAdd(&m.count, 1);
-                if (i < MERGE_CAP)
-                    m.pair[i] = make_int2(na, nc);
-                else
-                    g_unite(g, na, nc);
+        }
+        // the pair of the segment that covers each lane's site, per row
+        int ca = -1, cb = -1;  // at this lane in the previous face row of the same face
+#pragma unroll
+        for (int j = 0; j < MERGE_F; ++j) {
+            const int f = f0 + j;
+            if (f >= cy + cz) break;
+            const uint64_t sg = sgj[j];
+            const uint64_t o = lane_value64(lwa, j) & lane_value64(lwb, j);
+            const bool in = (o >> lane) & 1ull;
+            const uint64_t upto = sg & le;   // starts at or below this lane
+            const int cl = upto ? 63 - __clzll(upto) : lane;
+            const int xa = __shfl(sa[j], cl, 64), xb = __shfl(sb[j], cl, 64);
+            const bool seg = (sg >> lane) & 1ull;
+            const uint64_t below = sg & lt;
+            const int pl = below ? 63 - __clzll(below) : lane;
+            const int psa = __shfl(sa[j], pl, 64), psb = __shfl(sb[j], pl, 64);
+            if (seg) {
+                const bool first_of_face = f == 0 || f == cy;
+                const bool same_row = below && psa == sa[j] && psb == sb[j];
+                const bool same_col = j > 0 && !first_of_face && ca == sa[j] && cb == sb[j];
+                if (!same_row && !same_col) {
+                    const int bn = f < cy ? byn : bzn;
+                    if (sa[j] < g.cap && sb[j] < g.cap)
+                        merge_push(g, m, b * g.cap + sa[j], bn * g.cap + sb[j]);
+                    else
+                        set_err(g, ERR_FACE);
+                }
             }
+            ca = in ? xa : -1;
+            cb = in ? xb : -1;
         }
     }
     __syncthreads();
@@ -1098,14 +1124,97 @@ __device__ __forceinline__ void phase_rowpre(const Geo &g, int blk, int32_t *tmp
 }
 
 // --------------------------------------------------------------------------
-// phase: write -- label of every component slot of the brick: 1 + rank of
-// the cluster's root key site, from the node's root for boundary slots and
-// from the brick's own words for interior ones; sizes are written by the
-// slot that holds its cluster's key site.  Then every site takes the label
-// of its run's slot.  The first global inputs are requested before the first
-// wait: root positions of the boundary nodes, raw interior entries (to
-// s.par[bc, nc)) and run slots (to s.par[nc, nc + nr) when they fit, else
-// they are read from global memory per site).
+// phase: rank -- the final label of every node's cluster: 1 + the rank of the
+// cluster's key site (its lowest site, found by the roots phase) among all
+// key sites in linear order, from the root bit words and the per-word
+// prefixes.  The node that holds its cluster's key site (the root) also
+// writes the cluster's size.  Each thread takes RANK_U nodes at a time and
+// issues all their first loads, then all their dependent word loads, so one
+// brick costs two memory round trips.  Interior components are ranked by the
+// write phase from the brick's own words.
+// --------------------------------------------------------------------------
+
+constexpr int WG_RANK = 256;
+constexpr int RANK_U = 4;
+
+// Workgroups are dispatched to the eight XCDs in turn (workgroup i runs on XCD
+// i % 8).  This mapping hands all nbx bricks of a brick-row (one (by, bz)) to
+// the workgroups of one XCD, so that the partial cache lines which the bricks
+// of a brick-row write to one output range (the sizes of clusters whose key
+// sites share lattice rows) meet in that XCD's L2.  The grid is
+// xcd_grid(g) workgroups; the surplus ones get -1.
+constexpr int NXCD = 8;
+__host__ __device__ __forceinline__ int64_t xcd_grid(const Geo &g) {
+    const int64_t q = (int64_t)g.nby * g.nbz;
+    return (int64_t)NXCD * g.nbx * ((q + NXCD - 1) / NXCD);
+}
+__device__ __forceinline__ int xcd_brick(const Geo &g, int i) {
+    const int x = i % NXCD, j = i / NXCD;
+    const int q = x + NXCD * (j / g.nbx), bx = j % g.nbx;
+    return q < g.nby * g.nbz ? q * g.nbx + bx : -1;
+}
+
+__device__ __forceinline__ void phase_rank(const Geo &g, int b) {
+    const int bc = g.bcount[b];
+    const int64_t kmax = (n_sites(g) + 1) / 2;
+    const int64_t words = (int64_t)g.nb * g.R;
+    const int64_t wb = (int64_t)b * g.R;
+    const int n0 = b * g.cap;
+    for (int c0 = threadIdx.x; c0 < bc; c0 += RANK_U * WG_RANK) {
+        int64_t wi[RANK_U];
+        int bit[RANK_U];
+        int32_t sz[RANK_U];
+        bool own[RANK_U];
+#pragma unroll
+        for (int u = 0; u < RANK_U; ++u) {
+            const int c = c0 + u * WG_RANK;
+            wi[u] = -1;
+            bit[u] = 0;
+            sz[u] = 0;
+            own[u] = false;
+            if (c >= bc) continue;
+            const int64_t pos = g.nrootpos[n0 + c];
+            const int lp = g.nlpos[n0 + c];
+            wi[u] = pos >> 6;
+            bit[u] = (int)(pos & 63);
+            // the node holds its cluster's key site: it is the root
+            own[u] = wi[u] == wb + min(lp >> 6, g.R - 1) && bit[u] == (lp & 63);
+            sz[u] = g.nsize[n0 + c];
+        }
+        uint64_t rw[RANK_U];
+        int wp[RANK_U];
+#pragma unroll
+        for (int u = 0; u < RANK_U; ++u) {
+            const bool ok = wi[u] >= 0 && wi[u] < words;
+            rw[u] = ok ? g.root[wi[u]] : 0ull;
+            wp[u] = ok ? g.wpre[wi[u]] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < RANK_U; ++u) {
+            const int c = c0 + u * WG_RANK;
+            if (c >= bc) break;
+            if (wi[u] < 0 || wi[u] >= words) {
+                set_err(g, ERR_RANGE);
+                g.slab[n0 + c] = 0;
+                continue;
+            }
+            const int rank = wp[u] + __popcll(rw[u] & mask_lt(bit[u]));
+            g.slab[n0 + c] = rank + 1;
+            if (g.sizes && own[u]) {
+                if (rank >= 0 && (int64_t)rank < kmax)
+                    g.sizes[rank] = (int64_t)sz[u];
+                else
+                    set_err(g, ERR_RANGE);
+            }
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// phase: write -- every site takes the label of its run's component slot.
+// The brick's words, slot labels and run slots are loaded together (the run
+// slots to s.par[nc, nc + nr) when they fit, else they are read from global
+// memory per site), then the run offsets of the rows are counted.
 // --------------------------------------------------------------------------
 
 // Expand run labels to sites, one lattice row per wave and one site per
@@ -1140,101 +1249,37 @@ __device__ __forceinline__ void write_rows(const Geo &g, const Brick &k, const L
     }
 }
 
-// The labels of the brick's boundary components, each the final label of its
-// cluster: 1 + the rank of the cluster's root key site among all root sites
-// in linear order (root bit words and per-word prefixes).  s.par[c] = 1 +
-// rank for c < bc; the node holding its cluster's key site also writes the
-// cluster's size.  A thread takes nodes c0 and c0 + WG at a
-// time; the first pair's root positions are loaded at the start of the
-// write phase together with its other first loads.
-struct CanonPair {
-    int64_t pos[2];
-    int lp[2];
-};
-
-__device__ __forceinline__ CanonPair canon_load(const Geo &g, int b, int c0, int ncl) {
-    CanonPair p;
-    const int n0 = b * g.cap;
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int c = min(c0 + u * WG, ncl - 1);
-        p.pos[u] = c >= 0 ? g.nrootpos[n0 + c] : 0;
-        p.lp[u] = c >= 0 ? g.nlpos[n0 + c] : 0;
-    }
-    return p;
-}
-
-__device__ __forceinline__ void canon_rank(const Geo &g, int b, int c0, int ncl, const CanonPair &p, LdsBrick &s) {
-    const int64_t kmax = (n_sites(g) + 1) / 2;
-    const int64_t words = (int64_t)g.nb * g.R;
-    const int n0 = b * g.cap;
-    int64_t wi[2];
-    uint64_t rw[2];
-    int wp[2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        wi[u] = p.pos[u] >> 6;
-        const bool ok = wi[u] >= 0 && wi[u] < words;
-        rw[u] = ok ? g.root[wi[u]] : 0ull;
-        wp[u] = ok ? g.wpre[wi[u]] : 0;
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int c = c0 + u * WG;
-        if (c >= ncl) break;
-        if (wi[u] < 0 || wi[u] >= words) {
-            set_err(g, ERR_RANGE);
-            s.par[c] = 0;
-            continue;
-        }
-        const int rank = wp[u] + __popcll(rw[u] & mask_lt((int)(p.pos[u] & 63)));
-        s.par[c] = rank + 1;
-        // this node holds the cluster's key site: it is the root
-        if (g.sizes && wi[u] == (int64_t)b * g.R + min(p.lp[u] >> 6, g.R - 1) && (p.pos[u] & 63) == (p.lp[u] & 63)) {
-            if (rank >= 0 && (int64_t)rank < kmax)
-                g.sizes[rank] = g.nsize[n0 + c];
-            else
-                set_err(g, ERR_RANGE);
-        }
-    }
-}
-
 __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
     const Brick k = brick_of(g, b);
     const int t = threadIdx.x;
     const int R = g.R;
-    const int bc = g.bcount[b], nc = bc + g.icount[b], nr = g.nrun[b];
+    const int bc = g.bcount[b];
+    const int nc = min(bc + g.icount[b], MAXRUNS);
+    const int nr = g.nrun[b];
     const bool fit = nc + nr <= MAXRUNS;
     const uint16_t *L = g.runlab + (int64_t)b * g.runcap;
-    const int nbl = min(bc, MAXRUNS);  // boundary slots held in LDS
-    CanonPair first;
-    if (t < nbl) first = canon_load(g, b, t, nbl);
-    uint64_t w = 0;
     if (t < R) {
         const int64_t i = (int64_t)b * R + t;
-        w = g.occ[i];
-        s.occ[t] = w;
+        s.occ[t] = g.occ[i];
         s.rootw[t] = g.root[i];
         s.wpre[t] = g.wpre[i];
+        s.rowoff[t] = g.rowo[i];
     }
-    // Every load of the preamble is issued before the first wait: slot
-    // labels (boundary, then interior) and, when they fit, the run slots four
-    // to a 64-bit word (runcap is a multiple of four).
+    // Every load is issued before the first wait: slot labels (nodes, from
+    // the rank phase), raw interior entries and, when they fit, the run
+    // slots four to a 64-bit word (runcap is a multiple of four).
     {
-        const int ncl = min(nc, MAXRUNS);
-        for (int c0 = t; c0 < ncl; c0 += 4 * WG) {
+        for (int c0 = t; c0 < nc; c0 += 4 * WG) {
             int32_t v[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int c = c0 + u * WG;
-                v[u] = c >= ncl ? 0
-                       : c < bc ? 0 : (int32_t)g.icomp[(int64_t)b * g.icap + (c - bc)];
+                v[u] = c >= nc ? 0
+                       : c < bc ? g.slab[b * g.cap + c] : (int32_t)g.icomp[(int64_t)b * g.icap + (c - bc)];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int c = c0 + u * WG;
-                if (c >= bc && c < ncl) s.par[c] = v[u];
-            }
+            for (int u = 0; u < 4; ++u)
+                if (c0 + u * WG < nc) s.par[c0 + u * WG] = v[u];
         }
         if (fit) {
             const uint64_t *L4 = reinterpret_cast<const uint64_t *>(L);
@@ -1252,16 +1297,13 @@ __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
                 }
             }
         }
-        if (t < nbl) canon_rank(g, b, t, nbl, first, s);
-        for (int c0 = t + 2 * WG; c0 < nbl; c0 += 2 * WG) canon_rank(g, b, c0, nbl, canon_load(g, b, c0, nbl), s);
     }
-    int nruns;
-    const int off = block_excl_scan(__popcll(run_starts(w)), s.tmp, &nruns);
-    if (t < R) s.rowoff[t] = off;
+    __syncthreads();
 
-    // interior slots: rank of the key site from this brick's own words
+    // interior slots: rank of the key site from this brick's own words; the
+    // slot writes its cluster's size
     const int64_t kmax = (n_sites(g) + 1) / 2;
-    for (int c = bc + t; c < nc && c < MAXRUNS; c += WG) {
+    for (int c = bc + t; c < nc; c += WG) {
         const uint32_t u = (uint32_t)s.par[c];
         const int lp = (int)(u & ((1u << LPOS_BITS) - 1u));
         const int r = min(lp >> 6, R - 1);
@@ -1291,7 +1333,7 @@ __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
 // store of a phase as a possible write to them.
 // --------------------------------------------------------------------------
 
-constexpr int NPH = 7;  // local, merge, roots, rowsum, scanblk, rowpre, write
+constexpr int NPH = 8;  // local, merge, roots, rowsum, scanblk, rowpre, rank, write
 
 typedef const __attribute__((address_space(4))) Geo ConstGeo;
 typedef const __attribute__((address_space(4))) int32_t ConstI32;

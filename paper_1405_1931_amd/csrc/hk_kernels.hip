@@ -46,9 +46,17 @@ __global__ __launch_bounds__(WG) void k_rowpre(Geo g) {
 }
 
 
+// node labels carry little work per brick and no LDS: small workgroups keep
+// eight bricks per CU in flight
+__global__ __launch_bounds__(WG_RANK) __attribute__((amdgpu_waves_per_eu(8))) void k_rank(Geo g) {
+    const int b = xcd_brick(g, blockIdx.x);
+    if (b >= 0) phase_rank(g, b);
+}
+
 __global__ __launch_bounds__(WG) void k_write(Geo g) {
     __shared__ LdsBrick s;
-    phase_write(g, blockIdx.x, s);
+    const int b = xcd_brick(g, blockIdx.x);
+    if (b >= 0) phase_write(g, b, s);
 }
 
 __global__ void k_zero_i64(int64_t *p) {
@@ -56,7 +64,7 @@ __global__ void k_zero_i64(int64_t *p) {
 }
 
 const char *const kPhaseNames[kPhases] = {"k_local", "k_merge", "k_roots", "k_rowsum",
-                                          "k_scanblk", "k_rowpre", "k_write"};
+                                          "k_scanblk", "k_rowpre", "k_rank", "k_write"};
 
 hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev, int pk) {
     const dim3 blk(WG), small(WG_NODES);
@@ -81,8 +89,10 @@ hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev, int pk) {
     mark(5);
     hipLaunchKernelGGL(k_rowpre, dim3(g.nblk), blk, 0, st, g);
     mark(6);
-    hipLaunchKernelGGL(k_write, dim3(g.nb), blk, 0, st, g);
+    hipLaunchKernelGGL(k_rank, dim3((unsigned)xcd_grid(g)), dim3(WG_RANK), 0, st, g);
     mark(7);
+    hipLaunchKernelGGL(k_write, dim3((unsigned)xcd_grid(g)), blk, 0, st, g);
+    mark(8);
     return hipGetLastError();
 }
 
