@@ -568,11 +568,9 @@ __device__ __forceinline__ void walk_flatten(LdsBrick &s, int nruns) {
 }
 
 struct CoreOut {
-    int nruns;   // runs in the brick
-    int roots;   // components of the brick
-    int broots;  // components touching a shared face
-    int cpre;    // components whose root run precedes this thread's slice
-    int bpre;    // boundary components likewise
+    int nruns;       // runs in the brick
+    int btot, itot;  // boundary and interior components of the brick
+    int bpre, ipre;  // boundary / interior components whose root run precedes this thread's slice
     uint64_t rbits;  // start bits of this thread's root runs
 };
 
@@ -637,6 +635,7 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
     // run of a row when it reaches the brick's last x.  The start bits of
     // the slice's root runs are kept for the passes over roots only.
     uint64_t rbits = 0;
+    uint32_t ridm = 0;  // the slice's root runs, bit i for run first + i (a slice holds <= 16 runs)
     {
         const bool frow = (k.hyl && yl == 0) || (k.hyh && yl == k.ey - 1) || (k.hzl && zl == 0) ||
                           (k.hzh && zl == k.ez - 1);
@@ -651,7 +650,10 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
             m &= m - 1;
             const int v = s.par[id];
             const int r = (v == id || v < 0) ? id : v;
-            if (r == id) rbits |= 1ull << sb;
+            if (r == id) {
+                rbits |= 1ull << sb;
+                ridm |= 1u << (id - first);
+            }
             atomicAdd(&s.par[r], -(run_len(w, sb) << 16));
             if (frow || id == xlo || id == xhi) bflag_set(s, r);
             ++id;
@@ -659,22 +661,24 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
     }
     __syncthreads();
 
-    // per slice: roots (high half) and boundary roots (low half), < 2^15
-    // each; each root entry becomes -1 - size
-    int c = 0;
-    for (uint64_t m = rbits; m; m &= m - 1) {
-        const int id = offr + pop_le(st, __builtin_ctzll(m)) - 1;
-        s.par[id] = -1 - ((id - s.par[id]) >> 16);
-        c += (1 << 16) + (bflag_get(s, id) ? 1 : 0);
+    // the slice's components: its root runs, and those flagged boundary (the
+    // flags of the slice's runs are bits first, first + 1, ... of s.bflag);
+    // their prefix over the slices numbers the components in raster order
+    uint32_t bw = 0;
+    if (ridm) {
+        const int wi = first >> 5, sh = first & 31;
+        const uint64_t two = ((uint64_t)(wi + 1 < MAXRUNS / 32 ? s.bflag[wi + 1] : 0u) << 32) | s.bflag[wi];
+        bw = (uint32_t)(two >> sh) & ridm;
     }
+    const int cb = __popc(bw), ci = __popc(ridm) - cb;
     int tot;
-    const int pre = block_excl_scan(c, s.tmp, &tot);
+    const int pre = block_excl_scan((ci << 16) | cb, s.tmp, &tot);
     CoreOut out;
     out.nruns = total;
-    out.roots = tot >> 16;
-    out.broots = tot & 0xFFFF;
-    out.cpre = pre >> 16;
+    out.btot = tot & 0xFFFF;
+    out.itot = tot >> 16;
     out.bpre = pre & 0xFFFF;
+    out.ipre = pre >> 16;
     out.rbits = rbits;
     return out;
 }
@@ -684,6 +688,7 @@ __device__ __forceinline__ int root_of(const LdsBrick &s, int run) {
     const int v = s.par[run];
     return v < 0 ? run : v;
 }
+
 
 // --------------------------------------------------------------------------
 // phase: local -- label the brick, create its nodes, its interior component
@@ -716,57 +721,57 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
     if (t < R) g.occ[(int64_t)b * R + t] = s.occ[t];  // the words, for the later phases
     const CoreOut co = brick_core(g, k, s);
 
-    // component slots: boundary components take 0..B-1 (their node slots),
-    // interior components B..C-1; each root run's entry becomes -1 - slot
-    const int btot = co.broots;
+    // One pass over the root runs: boundary components (global nodes) take
+    // slots 0..B-1 and interior ones B..C-1, both in raster order of their
+    // root runs, and each writes its record: a node (key, position, size,
+    // parent) or an interior entry (size and key position).  Each root run's
+    // entry becomes -1 - slot.
+    const int btot = co.btot, itot = co.itot;
     if (row < R) {
+        int bi = co.bpre, ii = co.ipre;
         const uint64_t w = s.occ[row];
         const uint64_t st = run_starts(w);
         uint64_t m = co.rbits;  // root runs only
         const int offr = s.rowoff[row];
-        int bi = co.bpre;
-        int ii = co.cpre - co.bpre;
         const int yl = row & (g.BY - 1), zl = row >> g.lby;
         uint64_t rw = 0;
         while (m) {
             const int sb = __builtin_ctzll(m);
             m &= m - 1;
             const int id = offr + pop_le(st, sb) - 1;
-            const int v = s.par[id];  // -1 - size
-            {
-                int c;
-                if (bflag_get(s, id)) {
-                    c = bi++;
-                    if (c < g.cap) {
-                        const int n = b * g.cap + c;
-                        g.nkey[n] = (k.x0 + sb) + g.nx * ((k.y0 + yl) + g.ny * (k.z0 + zl));
-                        g.nlpos[n] = (uint16_t)(row * 64 + sb);
-                        g.nsize[n] = -1 - v;
-                        if (g.incr != 0) g.nsize0[n] = -1 - v;
-                        g.npar[n] = n;
-                    } else {
-                        set_err(g, ERR_CAP);
-                    }
+            const int size = (id - s.par[id]) >> 16;  // see the size pass
+            if (bflag_get(s, id)) {
+                const int c = bi++;
+                if (c < g.cap) {
+                    const int n = b * g.cap + c;
+                    g.nkey[n] = (k.x0 + sb) + g.nx * ((k.y0 + yl) + g.ny * (k.z0 + zl));
+                    g.nlpos[n] = (uint16_t)(row * 64 + sb);
+                    g.nsize[n] = size;
+                    if (g.incr != 0) g.nsize0[n] = size;
+                    g.npar[n] = n;
                 } else {
-                    // interior component: a finished cluster, key and size kept
-                    rw |= 1ull << sb;
-                    if (ii < g.icap)
-                        g.icomp[(int64_t)b * g.icap + ii] = ((uint32_t)(-1 - v) << LPOS_BITS) | (uint32_t)(row * 64 + sb);
-                    else
-                        set_err(g, ERR_CAP);
-                    c = btot + ii++;
+                    set_err(g, ERR_CAP);
                 }
                 s.par[id] = -1 - c;
+            } else {
+                // interior component: a finished cluster, key and size kept
+                const int i = ii++;
+                rw |= 1ull << sb;
+                if (i < g.icap)
+                    g.icomp[(int64_t)b * g.icap + i] = ((uint32_t)size << LPOS_BITS) | (uint32_t)(row * 64 + sb);
+                else
+                    set_err(g, ERR_CAP);
+                s.par[id] = -1 - (btot + i);
             }
         }
         if (rw) atomicOr((unsigned long long *)&s.rootw[row], (unsigned long long)rw);
     }
+    __syncthreads();
     if (t == 0) {
         g.bcount[b] = min(btot, g.cap);
-        g.icount[b] = min(co.roots - btot, g.icap);
+        g.icount[b] = min(itot, g.icap);
         g.nrun[b] = min(co.nruns, g.runcap);
     }
-    __syncthreads();
     if (t < R) {
         g.rowo[(int64_t)b * R + t] = (uint16_t)s.rowoff[t];
         g.root[(int64_t)b * R + t] = s.rootw[t];
