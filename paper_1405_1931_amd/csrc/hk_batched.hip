@@ -36,7 +36,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8))) void kb
     phase_local(g, i, s);
 }
 
-__global__ __launch_bounds__(WG_NODES) __attribute__((amdgpu_waves_per_eu(8))) void kb_merge(GroupView v) {
+__global__ __launch_bounds__(WG_MERGE) __attribute__((amdgpu_waves_per_eu(8))) void kb_merge(GroupView v) {
     __shared__ MergeLds m;
     int i;
     const Geo &g = locate(v, 1, blockIdx.x, &i);
@@ -268,7 +268,7 @@ int enqueue_batched(const hk_job *jobs, int n_jobs, const std::vector<Geo> &geos
     const dim3 blk(WG), small(WG_NODES);
     (void)hipGetLastError();
     hipLaunchKernelGGL(kb_local, dim3((unsigned)items[0]), blk, 0, stream, v);
-    hipLaunchKernelGGL(kb_merge, dim3((unsigned)items[1]), small, 0, stream, v);
+    hipLaunchKernelGGL(kb_merge, dim3((unsigned)items[1]), dim3(WG_MERGE), 0, stream, v);
     hipLaunchKernelGGL(kb_roots, dim3((unsigned)items[2]), small, 0, stream, v);
     hipLaunchKernelGGL(kb_rowsum, dim3((unsigned)items[3]), blk, 0, stream, v);
     hipLaunchKernelGGL(kb_scanblk, dim3((unsigned)items[4]), blk, 0, stream, v);

@@ -43,6 +43,8 @@ static_assert(64 * RMAX <= (1 << 14), "brick sizes are accumulated as size << 16
 // the node phases (global union-find, node labels) are latency bound and
 // carry little work per brick: small workgroups keep many bricks in flight
 constexpr int WG_NODES = 256;
+// the merge phase: two waves per brick, sixteen bricks per CU in flight
+constexpr int WG_MERGE = 128;
 constexpr uint16_t NOSITE = 0xFFFF;   // face-table entry of an empty site
 constexpr int GUARD = 1 << 22;        // bound on any retry/walk loop
 
@@ -1139,7 +1141,7 @@ __device__ __forceinline__ void phase_rowpre(const Geo &g, int blk, int32_t *tmp
 // write phase from the brick's own words.
 // --------------------------------------------------------------------------
 
-constexpr int WG_RANK = 256;
+constexpr int WG_RANK = 512;
 constexpr int RANK_U = 4;
 
 // Workgroups are dispatched to the eight XCDs in turn (workgroup i runs on XCD

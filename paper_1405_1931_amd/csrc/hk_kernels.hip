@@ -17,7 +17,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8))) void k_
     phase_local<PK>(g, blockIdx.x, s);
 }
 
-__global__ __launch_bounds__(WG_NODES) __attribute__((amdgpu_waves_per_eu(8))) void k_merge(Geo g) {
+__global__ __launch_bounds__(WG_MERGE) __attribute__((amdgpu_waves_per_eu(8))) void k_merge(Geo g) {
     __shared__ MergeLds m;
     phase_merge(g, blockIdx.x, m);
 }
@@ -79,7 +79,7 @@ hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev, int pk) {
         default: hipLaunchKernelGGL(k_local<PK_GT0>, dim3(g.nb), blk, 0, st, g); break;
     }
     mark(1);
-    hipLaunchKernelGGL(k_merge, dim3(g.nb), small, 0, st, g);
+    hipLaunchKernelGGL(k_merge, dim3(g.nb), dim3(WG_MERGE), 0, st, g);
     mark(2);
     hipLaunchKernelGGL(k_roots, dim3((g.nb + ROOTS_BRICKS - 1) / ROOTS_BRICKS), small, 0, st, g);
     mark(3);
