@@ -307,7 +307,11 @@ int hk_device_error(hipStream_t stream, int32_t *code);
  * admission and polls completion.
  *
  * Ownership: phi is the caller's and must stay valid and unchanged until
- * the request is done (hk_server_poll returns 1) or failed.  Output
+ * the request is done (hk_server_poll returns 1) or failed.  hk_server_submit
+ * takes phi as complete; when phi may still be in the making on a stream,
+ * submit it with hk_server_submit_after and that stream (the legacy null
+ * stream included): the server records an event on it at submission and
+ * the batch that reads phi waits for that event on the device.  Output
  * pointers from hk_server_result point into the arena and are valid until
  * hk_server_release of that ticket.  Results are identical to hk_label of
  * the same lattice alone.
@@ -320,9 +324,13 @@ int hk_device_error(hipStream_t stream, int32_t *code);
  * order).
  *
  * Errors: invalid arguments return HK_ERR_INVALID_ARG, a request larger
- * than the whole arena HK_ERR_TOO_LARGE (at submission).  A failed batch
- * marks each of its requests failed with the status (HK_ERR_HIP, or
- * HK_ERR_DEVICE when a device-side check fired); poll/wait/result return it.
+ * than the whole arena HK_ERR_TOO_LARGE (at submission).  Every request of
+ * a batch has its own device-side check word: a check that fires fails that
+ * request alone (HK_ERR_DEVICE) and the others of its batch complete.  A
+ * failure of the batch itself (a launch or copy that fails, or an
+ * asynchronous error its completion event reports) fails every request of
+ * that batch with HK_ERR_HIP and no other.  poll/wait/result return a failed
+ * request's status, wait also when the failure falls on its deadline.
  * All calls are thread-safe.
  * ------------------------------------------------------------------------
  */
@@ -355,6 +363,13 @@ int64_t hk_server_footprint(int32_t nx, int32_t ny, int32_t nz);
 int64_t hk_server_now_ns(void);
 int hk_server_submit(hk_server *s, const float *phi, int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask,
                      int64_t arrival_ns, uint64_t *ticket);
+int hk_server_submit_after(hk_server *s, const float *phi, int32_t nx, int32_t ny, int32_t nz,
+                           uint32_t periodic_mask, int64_t arrival_ns, hipStream_t producer, uint64_t *ticket);
+/* Simulated servers only: plant a failure on a waiting request, for tests
+ * of the failure paths.  HK_ERR_DEVICE fires that request's own device
+ * check; any other negative status is reported by the completion of the
+ * whole batch it runs in.  HK_ERR_INVALID_ARG on a real server. */
+int hk_server_sim_fail(hk_server *s, uint64_t ticket, int32_t status);
 /* 1 done, 0 waiting or running, < 0 failed (its status) or unknown ticket. */
 int hk_server_poll(hk_server *s, uint64_t ticket);
 /* Block until the request is done (HK_OK), failed (its status) or timeout_ns passed (HK_ERR_TIMEOUT). */

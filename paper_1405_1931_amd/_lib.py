@@ -101,6 +101,9 @@ _SIGS = {
     "hk_server_now_ns": (_I64, []),
     "hk_server_submit": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, ctypes.c_uint32, _I64,
                                         ctypes.POINTER(ctypes.c_uint64)]),
+    "hk_server_submit_after": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, ctypes.c_uint32, _I64, _P,
+                                              ctypes.POINTER(ctypes.c_uint64)]),
+    "hk_server_sim_fail": (ctypes.c_int, [_P, ctypes.c_uint64, _I32]),
     "hk_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64]),
     "hk_server_wait": (ctypes.c_int, [_P, ctypes.c_uint64, _I64]),
     "hk_server_drain": (ctypes.c_int, [_P, _I64]),

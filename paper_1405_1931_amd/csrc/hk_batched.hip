@@ -227,8 +227,10 @@ void release_batched() {
 // Enqueue the table upload and the eight grouped kernels of a validated
 // batch; `ws` holds at least the bytes validate_and_plan reported.  The
 // caller holds the workspace mutex (it guards the staging ring).
+// Job j's device-check word is at err + j * err_stride bytes (stride 0: one
+// word for the whole batch).
 int enqueue_batched(const hk_job *jobs, int n_jobs, const std::vector<Geo> &geos, char *ws, int32_t *err,
-                    hipStream_t stream) {
+                    int64_t err_stride, hipStream_t stream) {
     const TableLayout tl = table_layout(n_jobs);
     std::vector<char> img((size_t)tl.total, 0);
     int32_t *itoff = (int32_t *)(img.data() + tl.itoff);
@@ -251,7 +253,7 @@ int enqueue_batched(const hk_job *jobs, int n_jobs, const std::vector<Geo> &geos
         Geo g = geos[j];
         bind_lattice(&g, cursor);
         cursor += al(lattice_bytes(g));
-        g.err = err;
+        g.err = (int32_t *)((char *)err + (int64_t)j * err_stride);
         g.phi = jobs[j].phi;
         g.labels = jobs[j].labels;
         g.n_clusters = jobs[j].n_clusters;
@@ -310,7 +312,7 @@ int hk_label_batched(const hk_job *jobs, int32_t n_jobs, hipStream_t stream) {
     int32_t *err = nullptr;
     rc = acquire_workspace(stream, bytes, &base, &err);
     if (rc != HK_OK) return rc;
-    return enqueue_batched(jobs, n_jobs, geos, base, err, stream);
+    return enqueue_batched(jobs, n_jobs, geos, base, err, 0, stream);
 }
 
 }  // extern "C"

@@ -19,7 +19,14 @@
 //
 // A simulated executor (no HIP call at all) stands in for the device so that
 // the admission, batching and accounting logic can be exercised anywhere:
-// a batch then "runs" for fixed_ns + ns_per_site * sites of wall time.
+// a batch then "runs" for fixed_ns + ns_per_site * sites of wall time, and
+// a failure can be planted on a request (its own device check, or an error
+// of its whole batch) to exercise the failure paths.
+//
+// Failure isolation: every job of a batch has its own device-check word, so
+// a check that fires fails that job alone; an error of the batch itself (a
+// launch or copy that fails, or an asynchronous error reported by its
+// completion event) fails every job of that batch and no other.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,7 +51,7 @@ int64_t lattice_bytes(const Geo &g);
 std::mutex &workspace_mutex();
 int plan_batched(const hk_job *jobs, int n_jobs, std::vector<Geo> *geos, int64_t *bytes);
 int enqueue_batched(const hk_job *jobs, int n_jobs, const std::vector<Geo> &geos, char *ws, int32_t *err,
-                    hipStream_t stream);
+                    int64_t err_stride, hipStream_t stream);
 
 namespace {
 
@@ -117,23 +124,28 @@ struct Request {
     int64_t k = -1;
     int status = HK_OK;
     State state = State::Pending;
+    hipEvent_t ready = nullptr;  // recorded on the producer stream at submission, or null
+    int sim_fail = HK_OK;        // simulated servers: the failure planted on this request
 };
 
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
-    int64_t *host = nullptr;  // pinned: K of every job, then the device check word
+    int64_t *host = nullptr;  // pinned: K of every job, then every job's device check word
     bool busy = false;
     int64_t off = -1, bytes = 0;
     int64_t sim_done = 0;
+    int sim_error = HK_OK;  // simulated: the error the batch's completion reports
     std::vector<uint64_t> tickets;
 };
 
 // bytes of a batch block for n jobs whose lattice shares sum to ws: the
-// workspace (job table included), then K of every job, then the check word
+// workspace (job table included), then K of every job, then every job's
+// check word (8 bytes each)
+int64_t batch_tail_bytes(int n) { return al((int64_t)2 * n * 8); }
 int64_t batch_block_bytes(int n, int64_t ws_shares) {
     const int64_t table = al((int64_t)n * (int64_t)sizeof(Geo)) + al((int64_t)NPH * (n + 1) * 4);
-    return al(ws_shares + table) + al((int64_t)(n + 1) * 8);
+    return al(ws_shares + table) + batch_tail_bytes(n);
 }
 
 }  // namespace
@@ -165,19 +177,28 @@ struct hk_server {
     int64_t submitted = 0, completed = 0, failed = 0, batches = 0, batched_jobs = 0, sites_done = 0;
     int64_t first_launch = 0, last_done = 0;
 
+    std::vector<hipEvent_t> event_pool;  // request events, reused
+
     // ---------------------------------------------------------------- batches
-    bool slot_done(Slot &s) {
-        if (sim) return now_ns() >= s.sim_done;
-        return hipEventQuery(s.ev) == hipSuccess;
+    // 1: the batch completed; 0: still running; < 0: the batch failed with
+    // that status (any completion-event result but "not ready" is an error)
+    int slot_state(Slot &s) {
+        if (sim) return now_ns() >= s.sim_done ? (s.sim_error != HK_OK ? s.sim_error : 1) : 0;
+        const hipError_t e = hipEventQuery(s.ev);
+        if (e == hipSuccess) return 1;
+        if (e == hipErrorNotReady) return 0;
+        (void)hipGetLastError();
+        return HK_ERR_HIP;
     }
 
     void finish(Slot &s) {
         const int64_t t = now_ns();
         const int n = (int)s.tickets.size();
-        const int64_t check = sim ? 0 : s.host[n];
         for (int j = 0; j < n; ++j) {
             Request &r = reqs[s.tickets[j]];
             r.done = t;
+            // this job's own device check word
+            const int64_t check = sim ? (r.sim_fail == HK_ERR_DEVICE ? 1 : 0) : s.host[n + j];
             if (check != 0) {
                 r.state = State::Failed;
                 r.status = HK_ERR_DEVICE;
@@ -207,6 +228,18 @@ struct hk_server {
         arena.release(s.off, s.bytes);
         s.busy = false;
         s.tickets.clear();
+    }
+
+    hipEvent_t take_event() {
+        hipEvent_t e = nullptr;
+        if (!event_pool.empty()) {
+            e = event_pool.back();
+            event_pool.pop_back();
+        } else if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            (void)hipGetLastError();
+            e = nullptr;
+        }
+        return e;
     }
 
     // launch the longest prefix of the queue that fits this slot and the arena
@@ -250,13 +283,17 @@ struct hk_server {
         if (!first_launch) first_launch = t;
         if (sim) {
             int64_t sites = 0;
-            for (uint64_t tk : take) sites += reqs[tk].sites;
+            s.sim_error = HK_OK;
+            for (uint64_t tk : take) {
+                sites += reqs[tk].sites;
+                if (reqs[tk].sim_fail != HK_OK && reqs[tk].sim_fail != HK_ERR_DEVICE) s.sim_error = reqs[tk].sim_fail;
+            }
             s.sim_done = t + sim_fixed_ns + (int64_t)(sim_ns_per_site * (double)sites);
             return true;
         }
         // real device: job descriptors into the arena
         char *block = base + boff;
-        const int64_t ws_bytes = bbytes - al((int64_t)(n + 1) * 8);
+        const int64_t ws_bytes = bbytes - batch_tail_bytes(n);
         int64_t *kbuf = (int64_t *)(block + ws_bytes);
         std::vector<hk_job> jobs(n);
         for (int j = 0; j < n; ++j) {
@@ -268,13 +305,22 @@ struct hk_server {
         int64_t need = 0;
         int rc = plan_batched(jobs.data(), n, &geos, &need);
         if (rc == HK_OK && need > ws_bytes) rc = HK_ERR_NO_WORKSPACE;
-        if (rc == HK_OK && hipMemsetAsync(kbuf + n, 0, 8, s.stream) != hipSuccess) rc = HK_ERR_HIP;
+        // the batch reads each phi only after the work its producer stream had
+        // enqueued when the request was submitted
+        for (uint64_t tk : take) {
+            Request &r = reqs[tk];
+            if (!r.ready) continue;
+            if (rc == HK_OK && hipStreamWaitEvent(s.stream, r.ready, 0) != hipSuccess) rc = HK_ERR_HIP;
+            event_pool.push_back(r.ready);
+            r.ready = nullptr;
+        }
+        if (rc == HK_OK && hipMemsetAsync(kbuf + n, 0, (size_t)n * 8, s.stream) != hipSuccess) rc = HK_ERR_HIP;
         if (rc == HK_OK) {
             std::lock_guard<std::mutex> lk(workspace_mutex());
-            rc = enqueue_batched(jobs.data(), n, geos, block, (int32_t *)(kbuf + n), s.stream);
+            rc = enqueue_batched(jobs.data(), n, geos, block, (int32_t *)(kbuf + n), 8, s.stream);
         }
         if (rc == HK_OK &&
-            hipMemcpyAsync(s.host, kbuf, (size_t)(n + 1) * 8, hipMemcpyDeviceToHost, s.stream) != hipSuccess)
+            hipMemcpyAsync(s.host, kbuf, (size_t)(2 * n) * 8, hipMemcpyDeviceToHost, s.stream) != hipSuccess)
             rc = HK_ERR_HIP;
         if (rc == HK_OK && hipEventRecord(s.ev, s.stream) != hipSuccess) rc = HK_ERR_HIP;
         if (rc != HK_OK) {
@@ -295,11 +341,23 @@ struct hk_server {
         std::unique_lock<std::mutex> lk(mu);
         while (!stop) {
             bool progress = false;
-            for (Slot &s : slots)
-                if (s.busy && slot_done(s)) {
+            for (Slot &s : slots) {
+                if (!s.busy) continue;
+                const int st = slot_state(s);
+                if (st == 1) {
                     finish(s);
                     progress = true;
+                } else if (st < 0) {
+                    // the batch itself failed: its jobs, and only they, fail
+                    for (uint64_t tk : s.tickets) {
+                        Request &r = reqs[tk];
+                        arena.release(r.out_off, r.out_bytes);
+                        r.out_off = -1;
+                    }
+                    fail_batch(s, st);
+                    progress = true;
                 }
+            }
             if (progress) done_cv.notify_all();
             for (Slot &s : slots) {
                 if (queue.empty()) break;
@@ -363,7 +421,7 @@ int create(int64_t arena_bytes, int32_t n_slots, int32_t max_batch, bool sim, in
             void *h = nullptr;
             ok = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) == hipSuccess &&
                  hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) == hipSuccess &&
-                 hipHostMalloc(&h, (size_t)(max_batch + 1) * 8, hipHostMallocDefault) == hipSuccess;
+                 hipHostMalloc(&h, (size_t)(2 * max_batch) * 8, hipHostMallocDefault) == hipSuccess;
             sl.host = (int64_t *)h;
         }
         if (!ok) {
@@ -410,8 +468,12 @@ int64_t hk_server_footprint(int32_t nx, int32_t ny, int32_t nz) {
     return outb + batch_block_bytes(1, al(lattice_bytes(g)));
 }
 
-int hk_server_submit(hk_server *s, const float *phi, int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask,
-                     int64_t arrival_ns, uint64_t *ticket) {
+}  // extern "C"
+
+namespace {
+
+int submit(hk_server *s, const float *phi, int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask,
+           int64_t arrival_ns, bool after, hipStream_t producer, uint64_t *ticket) {
     if (!s || !ticket || (!phi && !s->sim)) return HK_ERR_INVALID_ARG;
     if (nx < 1 || ny < 1 || nz < 1 || periodic_mask > 7u) return HK_ERR_INVALID_ARG;
     const int64_t n = (int64_t)nx * ny * nz;
@@ -431,6 +493,15 @@ int hk_server_submit(hk_server *s, const float *phi, int32_t nx, int32_t ny, int
     if (r.out_bytes + batch_block_bytes(1, r.ws_bytes) > s->arena.size()) return HK_ERR_TOO_LARGE;
     {
         std::lock_guard<std::mutex> lk(s->mu);
+        if (!s->sim && after) {
+            // phi is complete once the producer stream's present work is
+            r.ready = s->take_event();
+            if (!r.ready || hipEventRecord(r.ready, producer) != hipSuccess) {
+                if (r.ready) s->event_pool.push_back(r.ready);
+                (void)hipGetLastError();
+                return HK_ERR_HIP;
+            }
+        }
         const uint64_t t = s->next_ticket++;
         s->reqs.emplace(t, r);
         s->queue.push_back(t);
@@ -439,6 +510,20 @@ int hk_server_submit(hk_server *s, const float *phi, int32_t nx, int32_t ny, int
     }
     s->work_cv.notify_one();
     return HK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hk_server_submit(hk_server *s, const float *phi, int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask,
+                     int64_t arrival_ns, uint64_t *ticket) {
+    return submit(s, phi, nx, ny, nz, periodic_mask, arrival_ns, false, nullptr, ticket);
+}
+
+int hk_server_submit_after(hk_server *s, const float *phi, int32_t nx, int32_t ny, int32_t nz,
+                           uint32_t periodic_mask, int64_t arrival_ns, hipStream_t producer, uint64_t *ticket) {
+    return submit(s, phi, nx, ny, nz, periodic_mask, arrival_ns, true, producer, ticket);
 }
 
 int hk_server_poll(hk_server *s, uint64_t ticket) {
@@ -462,6 +547,7 @@ int hk_server_wait(hk_server *s, uint64_t ticket, int64_t timeout_ns) {
         if (s->done_cv.wait_until(lk, until) == std::cv_status::timeout) {
             it = s->reqs.find(ticket);
             if (it != s->reqs.end() && it->second.state == State::Done) return HK_OK;
+            if (it != s->reqs.end() && it->second.state == State::Failed) return it->second.status;
             return HK_ERR_TIMEOUT;
         }
     }
@@ -508,6 +594,7 @@ int hk_server_release(hk_server *s, uint64_t ticket) {
         if (r.state == State::Running) return HK_ERR_INVALID_ARG;
         if (r.state == State::Pending) {
             s->queue.erase(std::find(s->queue.begin(), s->queue.end(), ticket));
+            if (r.ready) s->event_pool.push_back(r.ready);
         } else if (r.out_off >= 0) {
             s->arena.release(r.out_off, r.out_bytes);
         }
@@ -580,9 +667,21 @@ int hk_server_destroy(hk_server *s) {
             if (sl.ev) (void)hipEventDestroy(sl.ev);
             if (sl.stream) (void)hipStreamDestroy(sl.stream);
         }
+        for (auto &kv : s->reqs)
+            if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
+        for (hipEvent_t e : s->event_pool) (void)hipEventDestroy(e);
         if (s->base) (void)hipFree(s->base);
     }
     delete s;
+    return HK_OK;
+}
+
+int hk_server_sim_fail(hk_server *s, uint64_t ticket, int32_t status) {
+    if (!s || !s->sim || status >= 0) return HK_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end() || it->second.state != State::Pending) return HK_ERR_INVALID_ARG;
+    it->second.sim_fail = status;
     return HK_OK;
 }
 

@@ -57,15 +57,19 @@ class Server:
         return v
 
     # -------------------------------------------------------------- requests
-    def submit(self, phi, periodic=0, arrival_ns: int = 0) -> int:
-        """Queue one lattice (float32 cuda tensor (nz, ny, nx), contiguous)."""
-        from . import _check_phi, mask_of
+    def submit(self, phi, periodic=0, arrival_ns: int = 0, stream=None) -> int:
+        """Queue one lattice (float32 cuda tensor (nz, ny, nx), contiguous).
+
+        The batch that reads phi waits on the device for the work enqueued so
+        far on `stream` (default: torch's current stream), so phi may still be
+        in the making there."""
+        from . import _check_phi, _stream_handle, mask_of
 
         _check_phi(phi)
         nz, ny, nx = phi.shape
         t = ctypes.c_uint64()
-        rc = self._lib.hk_server_submit(self._h, phi.data_ptr(), nx, ny, nz, mask_of(periodic), int(arrival_ns),
-                                        ctypes.byref(t))
+        rc = self._lib.hk_server_submit_after(self._h, phi.data_ptr(), nx, ny, nz, mask_of(periodic),
+                                              int(arrival_ns), _stream_handle(stream), ctypes.byref(t))
         _lib.check(rc, "hk_server_submit")
         self._phi[t.value] = phi
         self._shape[t.value] = (nz, ny, nx)
@@ -82,6 +86,11 @@ class Server:
         _lib.check(rc, "hk_server_submit")
         self._shape[t.value] = (nz, ny, nx)
         return t.value
+
+    def sim_fail(self, ticket: int, status: int):
+        """Simulated servers: plant a failure on a waiting request (status
+        HK_ERR_DEVICE fails it alone, another negative status its batch)."""
+        _lib.check(self._lib.hk_server_sim_fail(self._h, ticket, int(status)), "hk_server_sim_fail")
 
     def poll(self, ticket: int) -> bool:
         rc = self._lib.hk_server_poll(self._h, ticket)

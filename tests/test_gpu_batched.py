@@ -82,8 +82,8 @@ def test_config5_stream(hk):
 
 
 def test_graph_capture_replay(hk):
-    """Capture one batched call in a hipGraph and replay it; every replay must
-    equal the eager result."""
+    """Capture one batched call in a hipGraph and replay it; the eager result
+    equals the oracle and every replay equals the eager result."""
     items = _mix(16, seed=21)
     jobs = []
     for phi_np, m in items:
@@ -97,6 +97,9 @@ def test_graph_capture_replay(hk):
         hk.label_batched_into(jobs)
     s.synchronize()
     eager = [(j[2].clone(), int(j[3].item()), j[4][: int(j[3].item())].clone()) for j in jobs]
+    for (phi_np, m), (el, ek, es) in zip(items, eager):
+        ol, ok, osz = oracle.label(phi_np, m)
+        assert ek == ok and np.array_equal(el.cpu().numpy(), ol) and np.array_equal(es.cpu().numpy(), osz)
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
         hk.label_batched_into(jobs)

@@ -168,3 +168,87 @@ def test_future_arrivals_are_held_until_due():
         for t in ts:
             lat = s.result(t)[3]
             assert 1 * MS <= lat < 9 * MS
+
+
+def _held(s, n, shape=(20, 20, 20), ahead_ns=50 * MS):
+    """n requests arriving together ahead of now (so they wait, and a
+    failure can be planted on them first); returns the tickets."""
+    at = s.now_ns() + ahead_ns
+    return [s.submit_shape(shape, arrival_ns=at) for _ in range(n)]
+
+
+def test_device_check_fails_only_its_own_request():
+    """Each request of a batch has its own device-check word: the planted
+    check fails that request alone, the others of the same batch complete."""
+    with Server(1 << 30, slots=1, max_batch=16, simulate=(1 * MS, 0.0)) as s:
+        tickets = _held(s, 8)
+        s.sim_fail(tickets[3], _lib.HK_ERR_DEVICE)
+        s.drain(30)
+        st = s.stats()
+        assert st["batches"] == 1, "the eight requests run as one batch"
+        assert st["completed"] == 7 and st["failed"] == 1
+        for j, t in enumerate(tickets):
+            if j == 3:
+                with pytest.raises(_lib.HkError) as e:
+                    s.result(t)
+                assert e.value.status == _lib.HK_ERR_DEVICE
+                with pytest.raises(_lib.HkError) as e:
+                    s.wait(t, 1.0)
+                assert e.value.status == _lib.HK_ERR_DEVICE
+                assert s._lib.hk_server_poll(s._h, t) == _lib.HK_ERR_DEVICE
+            else:
+                assert s.poll(t)
+                _, k, _, lat = s.result(t)
+                assert k == 0 and lat > 0
+            s.release(t)
+        assert s.stats()["arena_in_use"] == 0
+
+
+def test_batch_error_fails_that_batch_and_no_other():
+    """An error of a batch itself (as a failed launch or an asynchronous error
+    reported by its completion event) fails every request of that batch, and
+    the next batch runs normally."""
+    with Server(1 << 30, slots=1, max_batch=4, simulate=(1 * MS, 0.0)) as s:
+        tickets = _held(s, 8)
+        s.sim_fail(tickets[1], _lib.HK_ERR_HIP)
+        s.drain(30)
+        st = s.stats()
+        assert st["batches"] == 2 and st["failed"] == 4 and st["completed"] == 4
+        for j, t in enumerate(tickets):
+            if j < 4:
+                with pytest.raises(_lib.HkError) as e:
+                    s.wait(t, 1.0)
+                assert e.value.status == _lib.HK_ERR_HIP
+            else:
+                s.wait(t, 1.0)
+            s.release(t)
+        # failed requests gave their outputs back when their batch failed
+        assert s.stats()["arena_in_use"] == 0
+
+
+def test_wait_times_out_on_a_held_request_and_reports_a_failure_at_the_deadline():
+    with Server(1 << 30, slots=1, max_batch=4, simulate=(0, 0.0)) as s:
+        held = s.submit_shape((10, 10, 10), arrival_ns=s.now_ns() + 10_000 * MS)
+        with pytest.raises(_lib.HkError) as e:
+            s.wait(held, 0.01)
+        assert e.value.status == _lib.HK_ERR_TIMEOUT
+        s.release(held)  # withdrawn while waiting
+        # a failure that lands while the caller waits is reported as the
+        # failure, not as a time-out
+        t = _held(s, 1, ahead_ns=20 * MS)[0]
+        s.sim_fail(t, _lib.HK_ERR_DEVICE)
+        with pytest.raises(_lib.HkError) as e:
+            s.wait(t, 5.0)
+        assert e.value.status == _lib.HK_ERR_DEVICE
+        s.release(t)
+
+
+def test_sim_fail_is_refused_for_unknown_or_started_requests():
+    with Server(1 << 30, slots=1, max_batch=4, simulate=(0, 0.0)) as s:
+        t = s.submit_shape((8, 8, 8))
+        s.drain(10)
+        with pytest.raises(_lib.HkError):
+            s.sim_fail(t, _lib.HK_ERR_DEVICE)  # already done
+        with pytest.raises(_lib.HkError):
+            s.sim_fail(12345, _lib.HK_ERR_DEVICE)
+        s.release(t)
