@@ -288,6 +288,23 @@ const char *hk_phase_name(int32_t i);
 int hk_device_error(hipStream_t stream, int32_t *code);
 
 /*
+ * hk_debug_counters: synchronise `stream`, then write into counts[0..n) and
+ * clear the fallback counters of its workspace, summed over the hk_label,
+ * hk_label_pred and hk_label_batched calls on that stream since the last
+ * read.  Each counts the times a bounded fast structure was full and a
+ * slower exact path took over; results never depend on them:
+ *   [0] face pairs united where found (a brick's LDS pair list was full)
+ *   [1] node sizes added to their root directly (the LDS hash of a group of
+ *       bricks ran out of probes)
+ *   [2] bricks whose list of equivalences overflowed (their overlaps are
+ *       united again directly)
+ *   [3] bricks whose run slots did not fit the write phase's LDS (read from
+ *       global memory instead)
+ * Entries at index >= 4 are written as 0.
+ */
+int hk_debug_counters(hipStream_t stream, int64_t *counts, int32_t n);
+
+/*
  * ------------------------------------------------------------------------
  * Labelling server (continuous batching on one device).
  *

@@ -368,3 +368,15 @@ def device_error(stream=None) -> int:
     code = ctypes.c_int32(0)
     _lib.load().hk_device_error(_stream_handle(stream), ctypes.byref(code))
     return code.value
+
+
+DEBUG_COUNTERS = ("merge_direct", "roots_direct", "equiv_again", "runs_global")
+
+
+def debug_counters(stream=None) -> dict:
+    """Fallback counters of the workspace of `stream` since the last read
+    (hk_debug_counters): how often each bounded fast structure was full."""
+    out = (ctypes.c_int64 * len(DEBUG_COUNTERS))()
+    _lib.check(_lib.load().hk_debug_counters(_stream_handle(stream), out, len(DEBUG_COUNTERS)),
+               "hk_debug_counters")
+    return {name: int(out[i]) for i, name in enumerate(DEBUG_COUNTERS)}

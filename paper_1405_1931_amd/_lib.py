@@ -82,6 +82,7 @@ _SIGS = {
                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "hk_set_brick_for_shape": (ctypes.c_int, [ctypes.c_int32] * 5),
     "hk_device_error": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "hk_debug_counters": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32]),
     "hk_profile_enable": (ctypes.c_int, [ctypes.c_int32]),
     "hk_profile_read": (ctypes.c_int, [ctypes.POINTER(ctypes.c_float), ctypes.c_int32,
                                        ctypes.POINTER(ctypes.c_int32)]),

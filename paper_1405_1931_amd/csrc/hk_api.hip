@@ -26,9 +26,10 @@ int ceil_pow2(int v) {
     return p;
 }
 
+// ceil(log2(v)) for 1 <= v <= INT32_MAX (31 at most: 1 << 31 is not an int)
 int log2i(int v) {
     int l = 0;
-    while ((1 << l) < v) ++l;
+    while (l < 31 && (1 << l) < v) ++l;
     return l;
 }
 
@@ -44,9 +45,10 @@ uint32_t bucket_of(int nx, int ny, int nz) {
     return (uint32_t)(log2i(nx) | (log2i(ny) << 8) | (log2i(nz) << 16));
 }
 
-int64_t n_bricks(int nx, int ny, int nz, int by, int bz) {
-    return (int64_t)((nx + 63) / 64) * ((ny + by - 1) / by) * ((nz + bz - 1) / bz);
-}
+// ceil(a / b) without overflow for a up to INT32_MAX
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int64_t n_bricks(int nx, int ny, int nz, int by, int bz) { return cdiv(nx, 64) * cdiv(ny, by) * cdiv(nz, bz); }
 
 // Every brick costs a fixed latency, so bricks are as large as the lattice
 // allows; a lone small lattice trades some of that for more bricks in flight
@@ -96,9 +98,9 @@ bool make_geo(int nx, int ny, int nz, uint32_t mask, int by, int bz, Geo *g) {
     g->lby = log2i(by);
     g->lbz = log2i(bz);
     g->R = by * bz;
-    g->nbx = (nx + 63) / 64;
-    g->nby = (ny + by - 1) / by;
-    g->nbz = (nz + bz - 1) / bz;
+    g->nbx = (int)cdiv(nx, 64);
+    g->nby = (int)cdiv(ny, by);
+    g->nbz = (int)cdiv(nz, bz);
     const int64_t nb = (int64_t)g->nbx * g->nby * g->nbz;
     const int exm = std::min(64, nx);
     const int64_t c1 = 2 * ((g->R + 1) / 2) + 2 * ((exm * bz + 1) / 2) + 2 * ((exm * by + 1) / 2);
@@ -113,8 +115,8 @@ bool make_geo(int nx, int ny, int nz, uint32_t mask, int by, int bz, Geo *g) {
     g->icap = (int)c2;                   // components of a brick <= half its sites
     if (nb * (int64_t)g->runcap > ((int64_t)1 << 40) || nb * (int64_t)g->icap > ((int64_t)1 << 40)) return false;
     g->fstride = 2 * g->R;
-    g->rows = ny * nz;
-    g->nblk = (g->rows + WG - 1) / WG;
+    g->rows = ny * nz;  // <= N <= INT32_MAX
+    g->nblk = (int)(((int64_t)g->rows + WG - 1) / WG);
     return true;
 }
 
@@ -170,6 +172,12 @@ void bind(Geo *g, char *base, const Layout &L) {
     g->rowcnt = (int32_t *)(base + L.rowcnt);
     g->blksum = (int32_t *)(base + L.blksum);
 }
+
+// the fallback counters sit in the workspace's first block, after the
+// check word (the block is cleared when the workspace is allocated)
+constexpr int64_t kDbgOffset = 64;
+static_assert(kDbgOffset + DBG_N * 4 <= kErrBytes, "the counters fit the first block");
+uint32_t *dbg_counters(char *ws_base) { return (uint32_t *)(ws_base + kDbgOffset); }
 
 int check_shape(int32_t nx, int32_t ny, int32_t nz, uint32_t mask) {
     if (nx < 1 || ny < 1 || nz < 1 || mask > 7u) return HK_ERR_INVALID_ARG;
@@ -263,6 +271,7 @@ int plan_lattice_ext(int32_t nx, int32_t ny, int32_t nz, uint32_t mask, Geo *g) 
 }
 int64_t lattice_bytes(const Geo &g) { return layout_of(g, 0).total; }
 void bind_lattice(Geo *g, char *base) { bind(g, base, layout_of(*g, 0)); }
+uint32_t *workspace_dbg(int32_t *err) { return dbg_counters((char *)err); }
 int acquire_workspace(hipStream_t st, int64_t bytes, char **base, int32_t **err) {
     Workspace *ws = nullptr;
     const int rc = get_workspace(st, bytes, &ws);
@@ -341,6 +350,7 @@ int label_one(const void *field, int pk, int32_t tkey, int32_t nx, int32_t ny, i
     rc = get_workspace(stream, L.total, &ws);
     if (rc != HK_OK) return rc;
     g.err = (int32_t *)ws->base;
+    g.dbg = dbg_counters(ws->base);
     bind(&g, ws->base + kErrBytes, L);
     g.phi = (const float *)field;
     g.tkey = tkey;
@@ -575,6 +585,25 @@ int hk_profile_read(float *ms, int32_t n, int32_t *calls) {
 int32_t hk_phase_count(void) { return kPhases; }
 
 const char *hk_phase_name(int32_t i) { return (i >= 0 && i < kPhases) ? kPhaseNames[i] : ""; }
+
+int hk_debug_counters(hipStream_t stream, int64_t *counts, int32_t n) {
+    if (!counts || n < 0) return HK_ERR_INVALID_ARG;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return HK_ERR_HIP;
+    uint32_t v[DBG_N] = {0, 0, 0, 0};
+    {
+        std::lock_guard<std::mutex> lk(g_ws_mu);
+        auto it = g_ws.find({dev, stream});
+        if (it != g_ws.end() && it->second.base) {
+            if (hipStreamSynchronize(stream) != hipSuccess) return HK_ERR_HIP;
+            uint32_t *d = dbg_counters(it->second.base);
+            if (hipMemcpy(v, d, sizeof v, hipMemcpyDeviceToHost) != hipSuccess) return HK_ERR_HIP;
+            if (hipMemset(d, 0, sizeof v) != hipSuccess) return HK_ERR_HIP;
+        }
+    }
+    for (int i = 0; i < n; ++i) counts[i] = i < DBG_N ? (int64_t)v[i] : 0;
+    return HK_OK;
+}
 
 int hk_device_error(hipStream_t stream, int32_t *code) {
     int dev = 0;

@@ -94,6 +94,7 @@ int plan_lattice_ext(int32_t nx, int32_t ny, int32_t nz, uint32_t mask, Geo *g);
 int64_t lattice_bytes(const Geo &g);
 void bind_lattice(Geo *g, char *base);
 int acquire_workspace(hipStream_t st, int64_t bytes, char **base, int32_t **err);
+uint32_t *workspace_dbg(int32_t *err);
 std::mutex &workspace_mutex();
 
 namespace {
@@ -230,7 +231,7 @@ void release_batched() {
 // Job j's device-check word is at err + j * err_stride bytes (stride 0: one
 // word for the whole batch).
 int enqueue_batched(const hk_job *jobs, int n_jobs, const std::vector<Geo> &geos, char *ws, int32_t *err,
-                    int64_t err_stride, hipStream_t stream) {
+                    int64_t err_stride, uint32_t *dbg, hipStream_t stream) {
     const TableLayout tl = table_layout(n_jobs);
     std::vector<char> img((size_t)tl.total, 0);
     int32_t *itoff = (int32_t *)(img.data() + tl.itoff);
@@ -254,6 +255,7 @@ int enqueue_batched(const hk_job *jobs, int n_jobs, const std::vector<Geo> &geos
         bind_lattice(&g, cursor);
         cursor += al(lattice_bytes(g));
         g.err = (int32_t *)((char *)err + (int64_t)j * err_stride);
+        g.dbg = dbg;
         g.phi = jobs[j].phi;
         g.labels = jobs[j].labels;
         g.n_clusters = jobs[j].n_clusters;
@@ -312,7 +314,7 @@ int hk_label_batched(const hk_job *jobs, int32_t n_jobs, hipStream_t stream) {
     int32_t *err = nullptr;
     rc = acquire_workspace(stream, bytes, &base, &err);
     if (rc != HK_OK) return rc;
-    return enqueue_batched(jobs, n_jobs, geos, base, err, 0, stream);
+    return enqueue_batched(jobs, n_jobs, geos, base, err, 0, workspace_dbg(err), stream);
 }
 
 }  // extern "C"

@@ -48,6 +48,15 @@ constexpr int WG_MERGE = 128;
 constexpr uint16_t NOSITE = 0xFFFF;   // face-table entry of an empty site
 constexpr int GUARD = 1 << 22;        // bound on any retry/walk loop
 
+// Fallback counters: each counts the times a bounded fast structure was
+// full and the slower exact path took over (tests use them to show that a
+// fallback ran; the results are the same either way).
+constexpr int DBG_MERGE_DIRECT = 0;  // merge pairs united where found (LDS pair list full)
+constexpr int DBG_ROOTS_DIRECT = 1;  // node sizes added to the root directly (LDS hash probes exhausted)
+constexpr int DBG_EQUIV_AGAIN = 2;   // bricks whose equivalence list overflowed (overlaps united again)
+constexpr int DBG_RUNS_GLOBAL = 3;   // bricks whose run slots did not fit the write phase's LDS
+constexpr int DBG_N = 4;
+
 // device-side check codes (sticky flag, never a fault)
 constexpr int ERR_LOOP = 1;
 constexpr int ERR_CAP = 2;
@@ -93,6 +102,7 @@ struct Geo {
     int32_t *rowcnt;  // [rows] roots per lattice row
     int32_t *blksum;  // [nblk] roots per block of rows, then their prefix
     int32_t *err;     // sticky check flag
+    uint32_t *dbg;    // [DBG_N] fallback counters (see DBG_*), or null
     // incremental relabelling of a field that changes little between calls:
     // 0 off; 1 label every brick and keep the copies below; 2 as 1, but a
     // brick whose occupancy words equal those of the previous call keeps its
@@ -128,6 +138,9 @@ struct __align__(16) LdsBrick {
 // --------------------------------------------------------------------------
 
 __device__ __forceinline__ void set_err(const Geo &g, int code) { atomicOr(g.err, code); }
+__device__ __forceinline__ void count_dbg(const Geo &g, int i) {
+    if (g.dbg) atomicAdd(g.dbg + i, 1u);
+}
 
 // Occupancy predicates.  PK_GT0 is the cluster condition phi > 0 of Sec. 2;
 // the others let a caller label another set of sites (the capsule algorithm
@@ -619,6 +632,7 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
     }
     __syncthreads();
     if (stored < ne) {
+        if (t == 0) count_dbg(g, DBG_EQUIV_AGAIN);
         // no room for every equivalence: unite all overlaps again (idempotent)
         if (live && w) {
             if (yl > 0) unite_rows(g, s, row - 1, w, st, offr, q);
@@ -857,10 +871,12 @@ struct MergeLds {
 
 __device__ __forceinline__ void merge_push(const Geo &g, MergeLds &m, int na, int nc) {
     const int i = atomicAdd(&m.count, 1);
-    if (i < MERGE_CAP)
+    if (i < MERGE_CAP) {
         m.pair[i] = make_int2(na, nc);
-    else
+    } else {
         g_unite(g, na, nc);
+        count_dbg(g, DBG_MERGE_DIRECT);
+    }
 }
 
 __device__ __forceinline__ void phase_merge(const Geo &g, int b, MergeLds &m) {
@@ -1061,7 +1077,10 @@ __device__ __forceinline__ void phase_roots(const Geo &g, int b0, int nbr, int32
                         }
                         h = (h + 1) & (HT - 1);
                     }
-                    if (!done) atomicAdd(g.nsize + r, add);
+                    if (!done) {
+                        atomicAdd(g.nsize + r, add);
+                        count_dbg(g, DBG_ROOTS_DIRECT);
+                    }
                 }
             }
         }
@@ -1325,10 +1344,12 @@ __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
     }
     __syncthreads();
 
-    if (fit)
+    if (fit) {
         write_rows<true>(g, k, s, nc, L);
-    else
+    } else {
+        if (threadIdx.x == 0) count_dbg(g, DBG_RUNS_GLOBAL);
         write_rows<false>(g, k, s, nc, L);
+    }
 }
 
 // --------------------------------------------------------------------------

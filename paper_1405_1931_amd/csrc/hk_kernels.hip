@@ -81,7 +81,7 @@ hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev, int pk) {
     mark(1);
     hipLaunchKernelGGL(k_merge, dim3(g.nb), dim3(WG_MERGE), 0, st, g);
     mark(2);
-    hipLaunchKernelGGL(k_roots, dim3((g.nb + ROOTS_BRICKS - 1) / ROOTS_BRICKS), small, 0, st, g);
+    hipLaunchKernelGGL(k_roots, dim3((unsigned)(((int64_t)g.nb + ROOTS_BRICKS - 1) / ROOTS_BRICKS)), small, 0, st, g);
     mark(3);
     hipLaunchKernelGGL(k_rowsum, dim3(g.nblk), blk, 0, st, g);
     mark(4);

@@ -51,7 +51,7 @@ int64_t lattice_bytes(const Geo &g);
 std::mutex &workspace_mutex();
 int plan_batched(const hk_job *jobs, int n_jobs, std::vector<Geo> *geos, int64_t *bytes);
 int enqueue_batched(const hk_job *jobs, int n_jobs, const std::vector<Geo> &geos, char *ws, int32_t *err,
-                    int64_t err_stride, hipStream_t stream);
+                    int64_t err_stride, uint32_t *dbg, hipStream_t stream);
 
 namespace {
 
@@ -317,7 +317,7 @@ struct hk_server {
         if (rc == HK_OK && hipMemsetAsync(kbuf + n, 0, (size_t)n * 8, s.stream) != hipSuccess) rc = HK_ERR_HIP;
         if (rc == HK_OK) {
             std::lock_guard<std::mutex> lk(workspace_mutex());
-            rc = enqueue_batched(jobs.data(), n, geos, block, (int32_t *)(kbuf + n), 8, s.stream);
+            rc = enqueue_batched(jobs.data(), n, geos, block, (int32_t *)(kbuf + n), 8, nullptr, s.stream);
         }
         if (rc == HK_OK &&
             hipMemcpyAsync(s.host, kbuf, (size_t)(2 * n) * 8, hipMemcpyDeviceToHost, s.stream) != hipSuccess)

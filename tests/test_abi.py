@@ -163,3 +163,26 @@ def test_incremental_argument_errors_without_gpu(lib):
     assert lib.hk_incr_label(None, dummy, dummy, dummy, None, None, None) == _lib.HK_ERR_INVALID_ARG
     assert lib.hk_incr_device_error(None, None, None) == _lib.HK_ERR_INVALID_ARG
     lib.hk_incr_destroy(None)  # a no-op
+
+
+def test_int32_site_limit(lib):
+    """N <= INT32_MAX: one site more is refused before any device work, the
+    largest lattices below it are planned, and thin shapes whose row count
+    reaches INT32_MAX are either planned or refused (never an overflow)."""
+    dummy = ctypes.c_void_p(0x1000)
+    big = (2048, 1024, 1024)  # 2^31 = INT32_MAX + 1 sites
+    assert lib.hk_label(dummy, *big, 0, ctypes.c_void_p(0x2000), dummy, None, None) == _lib.HK_ERR_TOO_LARGE
+    assert lib.hk_workspace_bytes(*big) == _lib.HK_ERR_TOO_LARGE
+    jobs = (_lib.HkJob * 1)()
+    jobs[0] = _lib.HkJob(0x1000, *big, 0, 0x2000, 0x3000, None)
+    assert lib.hk_label_batched(jobs, 1, None) == _lib.HK_ERR_TOO_LARGE
+    assert lib.hk_server_footprint(*big) == _lib.HK_ERR_TOO_LARGE
+    # the largest lattice of the GPU tests: 2047 x 1024 x 1024 sites
+    n = 2047 * 1024 * 1024
+    assert n > 2 ** 30
+    assert lib.hk_workspace_bytes(2047, 1024, 1024) > 0
+    assert lib.hk_max_clusters(2047, 1024, 1024) == n // 2
+    assert lib.hk_max_clusters(2 ** 31 - 1, 1, 1) == 2 ** 30
+    for dims in [(1, 2 ** 31 - 1, 1), (1, 1, 2 ** 31 - 1), (2 ** 31 - 1, 1, 1)]:
+        v = lib.hk_workspace_bytes(*dims)
+        assert v > 0 or v == _lib.HK_ERR_TOO_LARGE, (dims, v)

@@ -48,7 +48,11 @@ def test_stripes_closed_form(hk, mask):
         x = torch.arange(nx, device="cuda", dtype=torch.int32).view(1, 1, nx)
         occ = (x % 2) == 0
         phi = torch.where(occ, 1.0, -1.0).to(torch.float32).expand(nz, ny, nx).contiguous()
+        hk.debug_counters()  # clear
         labels, k, sizes = hk.label(phi, mask)
+        # every brick took the overflow path (the fallback counter proves it)
+        nb = (nx // 64) * (ny // 16) * (nz // 16)
+        assert hk.debug_counters()["equiv_again"] == nb
         assert k == nx // 2
         assert bool((sizes == ny * nz).all())
         expect = torch.where(occ, torch.div(x, 2, rounding_mode="floor") + 1, 0).to(torch.int32)

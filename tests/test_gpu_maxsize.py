@@ -5,8 +5,9 @@ here; it covers the same patterns at smaller sizes in test_gpu_parity.py):
 
 * site checkerboard -- every occupied site its own cluster, K = N/2 (the
   Sec. 3 bound V/2), every size 1, label = 1 + #occupied sites before it;
-* block checkerboard with 64^3 blocks (the Sec. 3 benchmark lattice) --
-  K = 2048, every size 64^3, labels in closed form;
+* block checkerboards with b^3 blocks, b = 2, 4, 8, 64 (the Sec. 3
+  benchmark lattice, whose cluster count it varies) -- K = (1024/b)^3 / 2,
+  every size b^3, labels in closed form;
 * full and empty lattices -- K = 1 with size N, and K = 0.
 Both with and without periodic wrap (even lengths: the wraps join nothing
 in the checkerboards)."""
@@ -53,9 +54,10 @@ def test_site_checkerboard_1024(hk, mask):
 
 
 @pytest.mark.parametrize("mask", [0, 7])
-def test_block_checkerboard_1024(hk, mask):
-    print(f"[maxsize] block checkerboard 64^3 blocks, 1024^3 mask {mask}", flush=True)
-    n, b = N1, 64
+@pytest.mark.parametrize("b", [2, 4, 8, 64])
+def test_block_checkerboard_1024(hk, mask, b):
+    print(f"[maxsize] block checkerboard {b}^3 blocks, 1024^3 mask {mask}", flush=True)
+    n = N1
     nb = n // b
     z, y, x = axes(n)
     bi, bj, bk = torch.div(x, b, rounding_mode="floor"), torch.div(y, b, rounding_mode="floor"), \
