@@ -403,6 +403,22 @@ int hk_server_reset_stats(hk_server *s);
 /* Stop the scheduler, wait for running batches, free the arena; waiting requests are dropped. */
 int hk_server_destroy(hk_server *s);
 
+/*
+ * hk_label_noalloc: hk_label for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, hosts that forbid
+ * allocation).  Same arguments, outputs and argument checks as hk_label,
+ * computed by the same kernels, but the workspace is carved from a fixed
+ * 64 MiB device array inside the library (one per device, held until the
+ * process ends) and no call allocates or frees anything.  Lattices whose
+ * workspace does not fit it (a few million sites, depending on the shape)
+ * return HK_ERR_TOO_LARGE with no writes.  All calls on one device share
+ * the array: calls that overlap on one device race and must be serialised
+ * by the caller.  A device-side check that fires leaves *n_clusters equal to
+ * minus its code (hk_device_error does not see this array).
+ */
+int hk_label_noalloc(const float *phi, int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask, int32_t *labels,
+                     int64_t *n_clusters, int64_t *sizes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -65,6 +65,9 @@ _I64 = ctypes.c_int64
 _SIGS = {
     "hk_label": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32,
                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "hk_label_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
     "hk_label_pred": (ctypes.c_int, [_P, _I32, ctypes.c_float, _I32, _I32, _I32, ctypes.c_uint32, _P, _P, _P, _P]),
     "hk_incr_create": (ctypes.c_int, [_I32, _I32, _I32, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p)]),
     "hk_incr_label": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhk.so")
-SOURCES = ["hk_kernels.hip", "hk_api.hip", "hk_batched.hip", "hk_server.hip", "hk_tune.hip", "hk_classify.hip", "hk_droplets.hip"]
+SOURCES = ["hk_kernels.hip", "hk_api.hip", "hk_batched.hip", "hk_server.hip", "hk_tune.hip", "hk_classify.hip", "hk_droplets.hip", "hk_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -269,6 +269,10 @@ uint32_t brick_bucket(int nx, int ny, int nz) { return bucket_of(nx, ny, nz); }
 int plan_lattice_ext(int32_t nx, int32_t ny, int32_t nz, uint32_t mask, Geo *g) {
     return plan_lattice(nx, ny, nz, mask, g, true);
 }
+// a single lattice's plan, as hk_label makes it
+int plan_lattice_one(int32_t nx, int32_t ny, int32_t nz, uint32_t mask, Geo *g) {
+    return plan_lattice(nx, ny, nz, mask, g, false);
+}
 int64_t lattice_bytes(const Geo &g) { return layout_of(g, 0).total; }
 void bind_lattice(Geo *g, char *base) { bind(g, base, layout_of(*g, 0)); }
 uint32_t *workspace_dbg(int32_t *err) { return dbg_counters((char *)err); }
