@@ -122,11 +122,13 @@ _SIGS = {
 _lib = None
 
 
-def load(path: str = LIB_PATH):
-    """Load libhk.so; raises RuntimeError if it has not been built."""
+def load(path: str | None = None):
+    """Load libhk.so (LIB_PATH, read at the first call); raises RuntimeError
+    if it has not been built."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or LIB_PATH
     if not os.path.exists(path):
         raise RuntimeError(
             f"HIP library {path} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")

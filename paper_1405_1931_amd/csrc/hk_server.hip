@@ -577,8 +577,11 @@ int hk_server_result(hk_server *s, uint64_t ticket, int32_t **labels, int64_t *n
     const Request &r = it->second;
     if (r.state == State::Failed) return r.status;
     if (r.state != State::Done) return HK_ERR_INVALID_ARG;
-    if (labels) *labels = (int32_t *)(s->base + r.out_off);
-    if (sizes) *sizes = (int64_t *)(s->base + r.out_off + r.lab_bytes);
+    // a simulated server has no arena memory: its pointers are the offsets
+    // (computed as integers, since no object lies behind them)
+    const uintptr_t at = (uintptr_t)s->base + (uintptr_t)r.out_off;
+    if (labels) *labels = (int32_t *)at;
+    if (sizes) *sizes = (int64_t *)(at + (uintptr_t)r.lab_bytes);
     if (n_clusters) *n_clusters = r.k;
     if (latency_ns) *latency_ns = r.done - r.arrival;
     return HK_OK;
