@@ -150,6 +150,9 @@ constexpr int PK_GT = 0;   // float32 field > t
 constexpr int PK_EQ = 1;   // float32 field == t
 constexpr int PK_U8 = 2;   // uint8 field != 0
 constexpr int PK_GT0 = 3;  // float32 field > 0
+// value classes of the class test (bit k set: class k accepted): 7 positive
+// denormal, 8 positive normal, 9 +infinity
+constexpr int CLASS_POSITIVE = (1 << 7) | (1 << 8) | (1 << 9);
 
 // An integer key that orders float bit patterns as IEEE orders the values:
 // -|b| for negative values, b otherwise, so +0 and -0 share key 0 and
@@ -163,8 +166,9 @@ __host__ __device__ __forceinline__ int32_t order_key(uint32_t b) {
 template <int PK>
 __device__ __forceinline__ bool occupied_raw(uint32_t b, int32_t tkey) {
     if constexpr (PK == PK_GT0) {
-        // positive finite or +inf: not NaN, not +-0, not negative
-        return (int32_t)b > 0 && (int32_t)b <= 0x7f800000;
+        // positive denormal, normal or +inf (not NaN, not +-0, not negative):
+        // one class test of the raw bits, which no denormal mode changes
+        return __builtin_amdgcn_class(__uint_as_float(b), CLASS_POSITIVE);
     } else if constexpr (PK == PK_U8) {
         return b != 0u;
     } else {
@@ -497,10 +501,14 @@ __device__ __forceinline__ void fetch_rows(const Geo &g, const Brick &k, int bas
 template <int PK>
 __device__ __forceinline__ void ballot_rows(const Geo &g, int base, int r1, const uint32_t (&v)[OCC_U], LdsBrick &s) {
     const int lane = threadIdx.x & 63;
+    // all the batch's ballots first, then one store region for lane 0
+    uint64_t m[OCC_U];
 #pragma unroll
-    for (int j = 0; j < OCC_U; ++j) {
-        const uint64_t m = __ballot(occupied_raw<PK>(v[j], g.tkey));
-        if (lane == 0 && base + j < r1) s.occ[base + j] = m;
+    for (int j = 0; j < OCC_U; ++j) m[j] = __ballot(occupied_raw<PK>(v[j], g.tkey));
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < OCC_U; ++j)
+            if (base + j < r1) s.occ[base + j] = m[j];
     }
 }
 
@@ -532,17 +540,24 @@ __device__ __forceinline__ void bflag_set(LdsBrick &s, int id) { atomicOr(&s.bfl
 // to claim a run becomes its parent (rule 2, the label of the single labelled
 // neighbour); every further overlap is an equivalence (rule 3), stored after
 // the live runs in the par array as (a << 16 | b) while room lasts.
-__device__ __forceinline__ void link_rows(LdsBrick &s, int rp, uint64_t w, uint64_t st, int offr, int q, int nruns) {
+// The thread's work lies in its SLICE bits of the row, so the loop runs on
+// 32-bit words: the run ids count the starts below the slice once, then
+// the starts up to the segment within the slice.
+__device__ __forceinline__ void link_rows(LdsBrick &s, int rp, uint64_t w, uint64_t st, int first, int q, int nruns) {
+    const int sh = SLICE * q;
     const uint64_t wp = s.occ[rp];
     const uint64_t o = w & wp;
-    uint64_t seg = o & ~(o << 1) & slice_bits(q);
+    uint32_t seg = (uint32_t)((o & ~(o << 1)) >> sh);
+    if (!seg) return;
     const uint64_t stp = run_starts(wp);
-    const int offp = s.rowoff[rp];
+    const int cbase = s.rowoff[rp] + __popcll(stp & mask_lt(sh)) - 1;
+    const uint32_t st32 = (uint32_t)(st >> sh), stp32 = (uint32_t)(stp >> sh);
     while (seg) {
-        const int bb = __builtin_ctzll(seg);
+        const int bb = __builtin_ctz(seg);
         seg &= seg - 1;
-        const int a = offr + pop_le(st, bb) - 1;
-        const int c = offp + pop_le(stp, bb) - 1;
+        const uint32_t le = (2u << bb) - 1u;  // bits 0..bb (all 32 for bb = 31)
+        const int a = first - 1 + __popc(st32 & le);
+        const int c = cbase + __popc(stp32 & le);
         if (atomicCAS(s.par + a, a, c) != a) {
             const int e = atomicAdd(&s.tmp[20], 1);
             if (nruns + e < MAXRUNS) s.par[nruns + e] = (a << 16) | c;
@@ -614,8 +629,8 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
     // below (z-1); runs of different rows only meet there
     const int yl = row & (g.BY - 1), zl = row >> g.lby;
     if (live && w) {
-        if (yl > 0) link_rows(s, row - 1, w, st, offr, q, total);
-        if (zl > 0) link_rows(s, row - g.BY, w, st, offr, q, total);
+        if (yl > 0) link_rows(s, row - 1, w, st, first, q, total);
+        if (zl > 0) link_rows(s, row - g.BY, w, st, first, q, total);
     }
     __syncthreads();
     const int ne = s.tmp[20];
@@ -659,10 +674,10 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
         // last when it reaches the brick's last x (-1: none)
         const int xlo = k.hxl && (w & 1ull) ? offr : -1;
         const int xhi = k.hxh && ((w >> (k.ex - 1)) & 1ull) ? offr + __popcll(st) - 1 : -1;
-        uint64_t m = mine;
+        uint32_t m = (uint32_t)(mine >> (SLICE * q));
         int id = first;
         while (m) {
-            const int sb = __builtin_ctzll(m);
+            const int sb = __builtin_ctz(m) + SLICE * q;
             m &= m - 1;
             const int v = s.par[id];
             const int r = (v == id || v < 0) ? id : v;
@@ -747,14 +762,18 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
         int bi = co.bpre, ii = co.ipre;
         const uint64_t w = s.occ[row];
         const uint64_t st = run_starts(w);
-        uint64_t m = co.rbits;  // root runs only
-        const int offr = s.rowoff[row];
+        const int sh = SLICE * (t % TPR);
+        uint32_t m = (uint32_t)(co.rbits >> sh);  // root runs only
+        const uint32_t st32 = (uint32_t)(st >> sh);
+        // ids of the runs that start below this slice, minus one
+        const int base = s.rowoff[row] + __popcll(st & mask_lt(sh)) - 1;
         const int yl = row & (g.BY - 1), zl = row >> g.lby;
         uint64_t rw = 0;
         while (m) {
-            const int sb = __builtin_ctzll(m);
+            const int b32 = __builtin_ctz(m);
+            const int sb = b32 + sh;
             m &= m - 1;
-            const int id = offr + pop_le(st, sb) - 1;
+            const int id = base + __popc(st32 & ((2u << b32) - 1u));
             const int size = (id - s.par[id]) >> 16;  // see the size pass
             if (bflag_get(s, id)) {
                 const int c = bi++;
