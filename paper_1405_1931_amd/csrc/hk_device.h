@@ -86,8 +86,8 @@ struct Geo {
     int32_t *wpre;    // [nb][R] #cluster roots before this word, linear order
     uint16_t *face;   // [nb][fstride] node slot at each x-face site of each row
     int32_t *bcount;  // [nb] nodes used by each brick
-    int32_t *npar;    // [nb*cap] node parent
-    int32_t *nkey;    // [nb*cap] linear index of the node's lowest site
+    int32_t *npar;    // [nb*cap] node parent; at a root, -1 - the root's key (see g_find)
+    int32_t *nkey;    // [nb*cap] linear index of the node's lowest site (incremental calls only)
     int32_t *nsize;   // [nb*cap] sites in the node; at a root, the cluster
     uint16_t *nlpos;  // [nb*cap] brick-local position row*64 + x of the key
     int64_t *nrootpos; // [nb*cap] word index << 6 | bit of the node's root key site
@@ -331,40 +331,74 @@ __device__ __forceinline__ void l_unite(const Geo &g, int32_t *par, int a, int b
 // --------------------------------------------------------------------------
 // union-find over global nodes: a root is linked (CAS) below the root whose
 // key (linear index of its lowest site) is smaller, so each cluster's final
-// root is the node holding the cluster's lowest site.
+// root is the node holding the cluster's lowest site.  A root's entry holds
+// -1 - its key (keys are below 2^31 - 1, so the entry is negative) and any
+// other entry its parent's index: a find learns the root's key with the
+// load that shows it is a root, and a link is a CAS from -1 - key to the
+// new parent.
 //
 // Parent reads may be served by the XCD's own cache and so be stale: a stale
 // parent is still an ancestor (trees only ever merge), so a find on stale
-// values only takes a longer path.  Writes stay device-coherent: links are
-// CAS on the true entry, and a failed CAS returns the true parent, from
-// which the union carries on, so every retry climbs the true tree.
+// values only takes a longer path, and a stale root entry only makes the
+// link's CAS fail.  Writes stay device-coherent: links are CAS on the true
+// entry, and a failed CAS returns the true parent, from which the union
+// carries on, so every retry climbs the true tree.
 // --------------------------------------------------------------------------
 
 __device__ __forceinline__ int nd_ld(const int32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ __forceinline__ int g_find(const Geo &g, int x) {
+// Roots of two nodes at once, with their keys: the two pointer chases
+// advance in lockstep, so their loads are in flight together.  Paths are
+// halved: only non-root entries are rewritten, always to an ancestor.
+__device__ __forceinline__ void g_find2(const Geo &g, int &x, int &kx, int &y, int &ky) {
     int32_t *par = g.npar;
     const int nn = n_nodes(g);
+    bool dx = false, dy = false;
+    kx = ky = 0;
     for (int i = 0; i < GUARD; ++i) {
-        const int p = nd_ld(par + x);
-        if (p == x) return x;
-        if ((unsigned)p >= (unsigned)nn) {
+        if (dx && dy) return;
+        const int px = dx ? -1 : nd_ld(par + x);
+        const int py = dy ? -1 : nd_ld(par + y);
+        if (px >= nn || py >= nn) {
             set_err(g, ERR_RANGE);
-            return x;
+            return;
         }
-        const int gp = nd_ld(par + p);
-        if (gp == p) return p;
-        if ((unsigned)gp >= (unsigned)nn) {
+        const int gx = (dx || px < 0) ? -1 : nd_ld(par + px);
+        const int gy = (dy || py < 0) ? -1 : nd_ld(par + py);
+        if (gx >= nn || gy >= nn) {
             set_err(g, ERR_RANGE);
-            return p;
+            return;
         }
-        gl_st(par + x, gp);  // path halving; only non-roots are rewritten, always to an ancestor
-        x = gp;
+        if (!dx) {
+            if (px < 0) {
+                kx = -1 - px;
+                dx = true;
+            } else if (gx < 0) {
+                x = px;
+                kx = -1 - gx;
+                dx = true;
+            } else {
+                gl_st(par + x, gx);
+                x = gx;
+            }
+        }
+        if (!dy) {
+            if (py < 0) {
+                ky = -1 - py;
+                dy = true;
+            } else if (gy < 0) {
+                y = py;
+                ky = -1 - gy;
+                dy = true;
+            } else {
+                gl_st(par + y, gy);
+                y = gy;
+            }
+        }
     }
     set_err(g, ERR_LOOP);
-    return x;
 }
 
 __device__ __forceinline__ void g_unite(const Geo &g, int a, int b) {
@@ -374,67 +408,23 @@ __device__ __forceinline__ void g_unite(const Geo &g, int a, int b) {
         return;
     }
     for (int i = 0; i < GUARD; ++i) {
-        a = g_find(g, a);
-        b = g_find(g, b);
+        int ka, kb;
+        g_find2(g, a, ka, b, kb);
         if (a == b) return;
-        if (g.nkey[a] < g.nkey[b]) {
-            const int t = a;
+        if (ka < kb) {
+            const int t = a, tk = ka;
             a = b;
+            ka = kb;
             b = t;
+            kb = tk;
         }
-        const int old = atomicCAS(g.npar + a, a, b);
-        if (old == a) return;
+        const int old = atomicCAS(g.npar + a, -1 - ka, b);
+        if (old == -1 - ka) return;
         if ((unsigned)old >= (unsigned)nn) {
             set_err(g, ERR_RANGE);
             return;
         }
         a = old;  // a was linked meanwhile: carry on from its true parent
-    }
-    set_err(g, ERR_LOOP);
-}
-
-// Roots of two nodes at once: the two pointer chases advance in lockstep,
-// so their loads are in flight together (same halving rule as g_find).
-__device__ __forceinline__ void g_find2(const Geo &g, int &x, int &y) {
-    int32_t *par = g.npar;
-    const int nn = n_nodes(g);
-    bool dx = false, dy = false;
-    for (int i = 0; i < GUARD; ++i) {
-        if (dx && dy) return;
-        const int px = dx ? x : nd_ld(par + x);
-        const int py = dy ? y : nd_ld(par + y);
-        if ((unsigned)px >= (unsigned)nn || (unsigned)py >= (unsigned)nn) {
-            set_err(g, ERR_RANGE);
-            return;
-        }
-        const int gx = (dx || px == x) ? px : nd_ld(par + px);
-        const int gy = (dy || py == y) ? py : nd_ld(par + py);
-        if ((unsigned)gx >= (unsigned)nn || (unsigned)gy >= (unsigned)nn) {
-            set_err(g, ERR_RANGE);
-            return;
-        }
-        if (!dx) {
-            if (px == x) {
-                dx = true;
-            } else if (gx == px) {
-                x = px;
-                dx = true;
-            } else {
-                gl_st(par + x, gx);
-                x = gx;
-            }
-        }
-        if (!dy) {
-            if (py == y) {
-                dy = true;
-            } else if (gy == py) {
-                y = py;
-                dy = true;
-            } else {
-                gl_st(par + y, gy);
-                y = gy;
-            }
-        }
     }
     set_err(g, ERR_LOOP);
 }
@@ -741,7 +731,7 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
             const int bc = g.bcount[b];
             for (int c = t; c < bc; c += WG) {
                 const int n = b * g.cap + c;
-                g.npar[n] = n;
+                g.npar[n] = -1 - g.nkey[n];
                 g.nsize[n] = g.nsize0[n];
             }
             if (t < R) g.root[(int64_t)b * R + t] = g.rootw0[(int64_t)b * R + t];
@@ -779,11 +769,14 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
                 const int c = bi++;
                 if (c < g.cap) {
                     const int n = b * g.cap + c;
-                    g.nkey[n] = (k.x0 + sb) + g.nx * ((k.y0 + yl) + g.ny * (k.z0 + zl));
+                    const int key = (k.x0 + sb) + g.nx * ((k.y0 + yl) + g.ny * (k.z0 + zl));
                     g.nlpos[n] = (uint16_t)(row * 64 + sb);
                     g.nsize[n] = size;
-                    if (g.incr != 0) g.nsize0[n] = size;
-                    g.npar[n] = n;
+                    if (g.incr != 0) {
+                        g.nsize0[n] = size;
+                        g.nkey[n] = key;
+                    }
+                    g.npar[n] = -1 - key;
                 } else {
                     set_err(g, ERR_CAP);
                 }
@@ -1047,11 +1040,43 @@ static_assert(2 * HT <= MAXRUNS, "the hash must fit in the run array of LdsBrick
 // reach (the spanning cluster's) receives one global add per group of bricks.
 constexpr int ROOTS_MAX = 4;  // bricks one roots workgroup may take
 
+// q = v / d and *rem = v - q d, for 0 <= v < 2^31 and d >= 1; inv = 1.0 / d.
+// The product in double precision is within one of the true quotient, and
+// one correction step makes it exact.
+__device__ __forceinline__ int div_exact(int v, int d, double inv, int *rem) {
+    int q = (int)((double)v * inv);
+    int64_t r = (int64_t)v - (int64_t)q * d;
+    if (r < 0) {
+        --q;
+        r += d;
+    } else if (r >= d) {
+        ++q;
+        r -= d;
+    }
+    *rem = (int)r;
+    return q;
+}
+
+// word position (word index << 6 | bit) of the site whose linear index is key
+__device__ __forceinline__ int64_t key_word_pos(const Geo &g, int key, double inxy, double inx) {
+    int rxy, x;
+    const int z = div_exact(key, g.nx * g.ny, inxy, &rxy);
+    const int y = div_exact(rxy, g.nx, inx, &x);
+    const int bx = x >> 6, by = y >> g.lby, bz = z >> g.lbz;
+    const int r = (y & (g.BY - 1)) + g.BY * (z & (g.BZ - 1));
+    return (((int64_t)((bz * g.nby + by) * g.nbx + bx) * g.R + r) << 6) | (x & 63);
+}
+
 // rbits: LDS words of the workgroup's bricks (ROOTS_MAX * RMAX).  A root node
 // sets its root bit in its own brick's words, and only the workgroup that
 // takes a brick touches that brick's words in this phase, so the bits are
 // gathered in LDS and merged into the words with plain loads and stores
 // instead of one device-scope atomic per root.
+//
+// The nodes of all the workgroup's bricks form one index range, two nodes
+// per thread and step; a node's own position and size are requested with
+// its first parent load, and the root's key, which the find returns, gives
+// the position of the root's key site without a further load.
 __device__ __forceinline__ void phase_roots(const Geo &g, int b0, int nbr, int32_t *hash, uint64_t *rbits) {
     int32_t *hkey = hash, *hval = hash + HT;
     const int nt = blockDim.x;
@@ -1059,47 +1084,61 @@ __device__ __forceinline__ void phase_roots(const Geo &g, int b0, int nbr, int32
         hkey[i] = -1;
         hval[i] = 0;
     }
-    const int nw = min(nbr, g.nb - b0) * g.R;  // words of the workgroup's bricks
+    const int nbh = min(nbr, g.nb - b0);  // bricks of the workgroup
+    const int nw = nbh * g.R;              // their words
     for (int i = threadIdx.x; i < nw; i += nt) rbits[i] = 0ull;
+    // node counts of the bricks: c[j] nodes before brick b0 + j
+    int cpre[ROOTS_MAX + 1];
+    cpre[0] = 0;
+#pragma unroll
+    for (int j = 0; j < ROOTS_MAX; ++j) cpre[j + 1] = cpre[j] + (j < nbh ? g.bcount[b0 + j] : 0);
+    const int total = cpre[ROOTS_MAX];
+    const double inxy = 1.0 / ((double)g.nx * g.ny), inx = 1.0 / (double)g.nx;
     __syncthreads();
-    for (int b = b0; b < b0 + nbr && b < g.nb; ++b) {
-        const int cnt = g.bcount[b];
-        // two nodes per thread and step: i and i + nt
-        for (int i0 = threadIdx.x; i0 < cnt; i0 += 2 * nt) {
-            const int n0 = b * g.cap + i0;
-            const bool two = i0 + nt < cnt;
-            const int n1 = two ? n0 + nt : n0;
-            int r0 = n0, r1 = n1;
-            g_find2(g, r0, r1);
-    #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                if (u == 1 && !two) break;
-                const int n = u ? n1 : n0, r = u ? r1 : r0;
-                // position of the root's key site: word index << 6 | bit
-                const int lr = g.nlpos[r];
-                g.nrootpos[n] = (((int64_t)(r / g.cap) * g.R + min(lr >> 6, g.R - 1)) << 6) | (lr & 63);
-                if (r == n) {
-                    if ((lr >> 6) < g.R)
-                        atomicOr((unsigned long long *)(rbits + (b - b0) * g.R + (lr >> 6)), 1ull << (lr & 63));
-                    else
-                        set_err(g, ERR_RANGE);
-                } else {
-                    const int add = g.nsize[n];
-                    int h = (int)(((uint32_t)r * 2654435761u) >> (32 - HT_BITS));
-                    bool done = false;
-                    for (int probe = 0; probe < 64; ++probe) {
-                        const int old = atomicCAS(hkey + h, -1, r);
-                        if (old == -1 || old == r) {
-                            atomicAdd(hval + h, add);
-                            done = true;
-                            break;
-                        }
-                        h = (h + 1) & (HT - 1);
+    for (int i0 = threadIdx.x; i0 < total; i0 += 2 * nt) {
+        const bool two = i0 + nt < total;
+        int nd[2], bj[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int i = u ? (two ? i0 + nt : i0) : i0;
+            int j = 0;
+#pragma unroll
+            for (int q = 1; q < ROOTS_MAX; ++q) j += i >= cpre[q] ? 1 : 0;
+            bj[u] = j;
+            nd[u] = (b0 + j) * g.cap + (i - cpre[j]);
+        }
+        const int lp0 = g.nlpos[nd[0]], lp1 = g.nlpos[nd[1]];
+        const int sz0 = g.nsize[nd[0]], sz1 = g.nsize[nd[1]];
+        int r0 = nd[0], r1 = nd[1], k0, k1;
+        g_find2(g, r0, k0, r1, k1);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (u == 1 && !two) break;
+            const int n = nd[u], r = u ? r1 : r0, lr = u ? lp1 : lp0;
+            if (r == n) {
+                const int w = min(lr >> 6, g.R - 1);
+                g.nrootpos[n] = (((int64_t)(b0 + bj[u]) * g.R + w) << 6) | (lr & 63);
+                if ((lr >> 6) < g.R)
+                    atomicOr((unsigned long long *)(rbits + bj[u] * g.R + (lr >> 6)), 1ull << (lr & 63));
+                else
+                    set_err(g, ERR_RANGE);
+            } else {
+                g.nrootpos[n] = key_word_pos(g, u ? k1 : k0, inxy, inx);
+                const int add = u ? sz1 : sz0;
+                int h = (int)(((uint32_t)r * 2654435761u) >> (32 - HT_BITS));
+                bool done = false;
+                for (int probe = 0; probe < 64; ++probe) {
+                    const int old = atomicCAS(hkey + h, -1, r);
+                    if (old == -1 || old == r) {
+                        atomicAdd(hval + h, add);
+                        done = true;
+                        break;
                     }
-                    if (!done) {
-                        atomicAdd(g.nsize + r, add);
-                        count_dbg(g, DBG_ROOTS_DIRECT);
-                    }
+                    h = (h + 1) & (HT - 1);
+                }
+                if (!done) {
+                    atomicAdd(g.nsize + r, add);
+                    count_dbg(g, DBG_ROOTS_DIRECT);
                 }
             }
         }
