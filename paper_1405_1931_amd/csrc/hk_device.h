@@ -526,10 +526,11 @@ __device__ __forceinline__ bool bflag_get(const LdsBrick &s, int id) { return (s
 __device__ __forceinline__ void bflag_set(LdsBrick &s, int id) { atomicOr(&s.bflag[id >> 5], 1u << (id & 31)); }
 
 // The serial pass's rules, applied to the overlap segments of a row with its
-// predecessor row rp that start in slice q: the first overlapping run of rp
-// to claim a run becomes its parent (rule 2, the label of the single labelled
-// neighbour); every further overlap is an equivalence (rule 3), stored after
-// the live runs in the par array as (a << 16 | b) while room lasts.
+// predecessor row rp that start in slice q: the first overlap to claim a run
+// links it into the tree of the overlapping run of rp (rule 2, the label of
+// the single labelled neighbour); every further overlap is an equivalence
+// (rule 3), stored after the live runs in the par array as (a << 16 | b)
+// while room lasts.
 // The thread's work lies in its SLICE bits of the row, so the loop runs on
 // 32-bit words: the run ids count the starts below the slice once, then
 // the starts up to the segment within the slice.
@@ -547,7 +548,9 @@ __device__ __forceinline__ void link_rows(LdsBrick &s, int rp, uint64_t w, uint6
         seg &= seg - 1;
         const uint32_t le = (2u << bb) - 1u;  // bits 0..bb (all 32 for bb = 31)
         const int a = first - 1 + __popc(st32 & le);
-        const int c = cbase + __popc(stp32 & le);
+        // link to c's parent (c itself while c is unlinked): an ancestor of c
+        // and an earlier run, which keeps the trees about half as deep
+        const int c = lds_ld(s.par + cbase + __popc(stp32 & le));
         if (atomicCAS(s.par + a, a, c) != a) {
             const int e = atomicAdd(&s.tmp[20], 1);
             if (nruns + e < MAXRUNS) s.par[nruns + e] = (a << 16) | c;
@@ -744,55 +747,102 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
 
     // One pass over the root runs: boundary components (global nodes) take
     // slots 0..B-1 and interior ones B..C-1, both in raster order of their
-    // root runs, and each writes its record: a node (key, position, size,
-    // parent) or an interior entry (size and key position).  Each root run's
-    // entry becomes -1 - slot.
+    // root runs, and each root run's entry becomes -1 - slot.  Each slot's
+    // record -- size << LPOS_BITS | key position -- is staged in LDS after
+    // the runs when it fits (almost always: C <= runs, and the array holds
+    // MAXRUNS entries), and written out by slot once all are known, one
+    // coalesced pass: a node (position, size and the parent entry that holds
+    // its key) or an interior entry (the record itself).  Otherwise the pass
+    // writes each record where it finds it.
     const int btot = co.btot, itot = co.itot;
+    const int ncomp = btot + itot;
+    const bool staged = co.nruns + ncomp <= MAXRUNS;
+    uint32_t *stage = reinterpret_cast<uint32_t *>(s.par + co.nruns);
     if (row < R) {
         int bi = co.bpre, ii = co.ipre;
         const uint64_t w = s.occ[row];
         const uint64_t st = run_starts(w);
-        const int sh = SLICE * (t % TPR);
+        const int q = t % TPR, sh = SLICE * q;
         uint32_t m = (uint32_t)(co.rbits >> sh);  // root runs only
         const uint32_t st32 = (uint32_t)(st >> sh);
         // ids of the runs that start below this slice, minus one
         const int base = s.rowoff[row] + __popcll(st & mask_lt(sh)) - 1;
-        const int yl = row & (g.BY - 1), zl = row >> g.lby;
-        uint64_t rw = 0;
-        while (m) {
-            const int b32 = __builtin_ctz(m);
-            const int sb = b32 + sh;
-            m &= m - 1;
-            const int id = base + __popc(st32 & ((2u << b32) - 1u));
-            const int size = (id - s.par[id]) >> 16;  // see the size pass
-            if (bflag_get(s, id)) {
-                const int c = bi++;
-                if (c < g.cap) {
-                    const int n = b * g.cap + c;
-                    const int key = (k.x0 + sb) + g.nx * ((k.y0 + yl) + g.ny * (k.z0 + zl));
-                    g.nlpos[n] = (uint16_t)(row * 64 + sb);
-                    g.nsize[n] = size;
-                    if (g.incr != 0) {
-                        g.nsize0[n] = size;
-                        g.nkey[n] = key;
-                    }
-                    g.npar[n] = -1 - key;
-                } else {
-                    set_err(g, ERR_CAP);
-                }
+        const int lp0 = row * 64 + sh;  // key position of the slice's bit 0
+        uint32_t rw = 0;                 // root bits of the slice's interior components
+        if (staged) {
+            while (m) {
+                const int b32 = __builtin_ctz(m);
+                m &= m - 1;
+                const int id = base + __popc(st32 & ((2u << b32) - 1u));
+                const int size = (id - s.par[id]) >> 16;  // see the size pass
+                const bool bnd = bflag_get(s, id);
+                const int c = bnd ? bi++ : btot + ii++;
+                rw |= bnd ? 0u : 1u << b32;
+                stage[c] = ((uint32_t)size << LPOS_BITS) | (uint32_t)(lp0 + b32);
                 s.par[id] = -1 - c;
-            } else {
-                // interior component: a finished cluster, key and size kept
-                const int i = ii++;
-                rw |= 1ull << sb;
-                if (i < g.icap)
-                    g.icomp[(int64_t)b * g.icap + i] = ((uint32_t)size << LPOS_BITS) | (uint32_t)(row * 64 + sb);
-                else
-                    set_err(g, ERR_CAP);
-                s.par[id] = -1 - (btot + i);
+            }
+        } else {
+            const int yl = row & (g.BY - 1), zl = row >> g.lby;
+            while (m) {
+                const int b32 = __builtin_ctz(m);
+                const int sb = b32 + sh;
+                m &= m - 1;
+                const int id = base + __popc(st32 & ((2u << b32) - 1u));
+                const int size = (id - s.par[id]) >> 16;  // see the size pass
+                if (bflag_get(s, id)) {
+                    const int c = bi++;
+                    if (c < g.cap) {
+                        const int n = b * g.cap + c;
+                        const int key = (k.x0 + sb) + g.nx * ((k.y0 + yl) + g.ny * (k.z0 + zl));
+                        g.nlpos[n] = (uint16_t)(row * 64 + sb);
+                        g.nsize[n] = size;
+                        if (g.incr != 0) {
+                            g.nsize0[n] = size;
+                            g.nkey[n] = key;
+                        }
+                        g.npar[n] = -1 - key;
+                    } else {
+                        set_err(g, ERR_CAP);
+                    }
+                    s.par[id] = -1 - c;
+                } else {
+                    // interior component: a finished cluster, key and size kept
+                    const int i = ii++;
+                    rw |= 1u << b32;
+                    if (i < g.icap)
+                        g.icomp[(int64_t)b * g.icap + i] = ((uint32_t)size << LPOS_BITS) | (uint32_t)(row * 64 + sb);
+                    else
+                        set_err(g, ERR_CAP);
+                    s.par[id] = -1 - (btot + i);
+                }
             }
         }
-        if (rw) atomicOr((unsigned long long *)&s.rootw[row], (unsigned long long)rw);
+        if (rw) atomicOr(reinterpret_cast<uint32_t *>(&s.rootw[row]) + q, rw);
+    }
+    __syncthreads();
+    if (staged) {
+        const uint32_t pmask = (1u << LPOS_BITS) - 1u;
+        const int nbw = min(btot, g.cap);
+        int32_t *npar = g.npar + b * g.cap;
+        int32_t *nsize = g.nsize + b * g.cap;
+        uint16_t *nlpos = g.nlpos + b * g.cap;
+        for (int c = t; c < nbw; c += WG) {
+            const uint32_t rec = stage[c];
+            const int lp = (int)(rec & pmask), size = (int)(rec >> LPOS_BITS);
+            const int r = lp >> 6;
+            const int key = (k.x0 + (lp & 63)) + g.nx * ((k.y0 + (r & (g.BY - 1))) + g.ny * (k.z0 + (r >> g.lby)));
+            nlpos[c] = (uint16_t)lp;
+            nsize[c] = size;
+            npar[c] = -1 - key;
+            if (g.incr != 0) {
+                g.nsize0[b * g.cap + c] = size;
+                g.nkey[b * g.cap + c] = key;
+            }
+        }
+        const int niw = min(itot, g.icap);
+        uint32_t *icomp = g.icomp + (int64_t)b * g.icap;
+        for (int i = t; i < niw; i += WG) icomp[i] = stage[btot + i];
+        if (t == 0 && (btot > g.cap || itot > g.icap)) set_err(g, ERR_CAP);
     }
     __syncthreads();
     if (t == 0) {
