@@ -42,7 +42,7 @@ static_assert(RMAX <= 512, "run ids, positions and sizes are packed for at most 
 static_assert(64 * RMAX <= (1 << 14), "brick sizes are accumulated as size << 16 in an int32");
 // the node phases (global union-find, node labels) are latency bound and
 // carry little work per brick: small workgroups keep many bricks in flight
-constexpr int WG_NODES = 256;
+constexpr int WG_NODES = 512;
 // the merge phase: two waves per brick, sixteen bricks per CU in flight
 constexpr int WG_MERGE = 128;
 constexpr uint16_t NOSITE = 0xFFFF;   // face-table entry of an empty site
