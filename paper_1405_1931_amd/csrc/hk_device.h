@@ -233,15 +233,24 @@ __device__ __forceinline__ uint64_t wave_uniform64(uint64_t v) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// inclusive prefix sum over the 64 lanes of a wave, with DPP moves: shifts
+// by 1, 2, 4 and 8 lanes within each row of 16 lanes, then lane 15 of rows 0
+// and 2 added to rows 1 and 3, then lane 31 to rows 2 and 3 (a lane whose
+// source is outside the row or whose row is masked off adds 0)
+__device__ __forceinline__ int wave_incl_scan(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
+}
+
 // exclusive prefix sum over the WG threads of the workgroup; all threads call
 __device__ __forceinline__ int block_excl_scan(int v, int32_t *tmp, int *total) {
     const int lane = threadIdx.x & 63, w = wave_uniform(threadIdx.x >> 6);
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
+    const int x = wave_incl_scan(v);
     if (lane == 63) tmp[w] = x;
     __syncthreads();
     int base = 0, tot = 0;
