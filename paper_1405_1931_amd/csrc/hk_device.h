@@ -959,32 +959,8 @@ __device__ __forceinline__ void phase_merge(const Geo &g, int b, MergeLds &m) {
     const int bxn = k.bx > 0 ? b - 1 : b + (g.nbx - 1);
     const int byn = k.by > 0 ? b - g.nbx : b + (g.nby - 1) * g.nbx;
     const int bzn = k.bz > 0 ? b - g.nbx * g.nby : b + (g.nbz - 1) * g.nbx * g.nby;
-
-    if (k.hxl) {
-        const uint16_t *Fs = g.face + (int64_t)b * g.fstride + f_xlo(g);
-        const uint16_t *Gs = g.face + (int64_t)bxn * g.fstride + f_xhi(g);
-        for (int e0 = 64 * wv; e0 < g.R; e0 += 64 * nw) {
-            const int e = e0 + lane;
-            const int yl = e & (g.BY - 1), zl = e >> g.lby;
-            const bool valid = e < g.R && yl < k.ey && zl < k.ez;
-            uint16_t fa = NOSITE, fc = NOSITE;
-            if (valid) {
-                fa = Fs[e];
-                fc = Gs[e];
-            }
-            const bool both = fa != NOSITE && fc != NOSITE;
-            // row e - 1 (same plane when yl > 0) is in lane - 1, except at
-            // lane 0 of a chunk that starts inside a y row (BY > 64)
-            bool prev = __shfl_up((int)both, 1, 64) != 0;
-            if (lane == 0) prev = valid && yl > 0 && Fs[e - 1] != NOSITE && Gs[e - 1] != NOSITE;
-            if (both && !(yl > 0 && prev)) {
-                if (fa < g.cap && fc < g.cap)
-                    merge_push(g, m, b * g.cap + fa, bxn * g.cap + fc);
-                else
-                    set_err(g, ERR_FACE);
-            }
-        }
-    }
+    const uint16_t *Fs = g.face + (int64_t)b * g.fstride + f_xlo(g);
+    const uint16_t *Gs = g.face + (int64_t)bxn * g.fstride + f_xhi(g);
 
     // extents of the neighbours across the low y and z faces (a wrap pairs
     // the brick with the last brick of the axis, which may be partial)
@@ -992,15 +968,23 @@ __device__ __forceinline__ void phase_merge(const Geo &g, int b, MergeLds &m) {
     const int ezn = k.bz > 0 ? g.BZ : g.nz - (g.nbz - 1) * g.BZ;
     const int cy = k.hyl ? k.ez : 0, cz = k.hzl ? k.ey : 0;
     const uint64_t le = mask_le(lane), lt = mask_lt(lane);
-    // Each wave takes MERGE_F consecutive face rows at a time: lane j loads
-    // the words and first-run offsets of face row j (one round trip), then
-    // the run slots of every segment start of the MERGE_F rows are requested
-    // together (a second round trip).  Consecutive face rows of one face are
-    // neighbours across the face's other axis, so a lane at a segment start
-    // drops its pair when the same site of the face row before had the same
-    // pair (a cluster that crosses a face meets the same two components row
-    // after row).
-    for (int f0 = MERGE_F * wv; f0 < cy + cz; f0 += MERGE_F * nw) {
+    // Step `it` of a wave takes x-face chunk `it` (64 rows) and y/z face
+    // group `it` (MERGE_F face rows); the loads of both that need nothing
+    // else are issued together, then the run slots of the y/z segments.
+    const int nxc = k.hxl ? (g.R + 63) >> 6 : 0;
+    const int nyz = (cy + cz + MERGE_F - 1) / MERGE_F;
+    for (int it = wv; it < max(nxc, nyz); it += nw) {
+        // x face: one row per lane
+        const int e = 64 * it + lane;
+        const int yl = e & (g.BY - 1), zl = e >> g.lby;
+        const bool xvalid = it < nxc && e < g.R && yl < k.ey && zl < k.ez;
+        uint16_t fa = NOSITE, fc = NOSITE;
+        if (xvalid) {
+            fa = Fs[e];
+            fc = Gs[e];
+        }
+        // y/z faces: lane j < MERGE_F loads the words and first-run offsets of face row f0 + j
+        const int f0 = MERGE_F * it;
         uint64_t lwa = 0, lwb = 0;
         int loa = 0, lob = 0;
         {
@@ -1022,6 +1006,27 @@ __device__ __forceinline__ void phase_merge(const Geo &g, int b, MergeLds &m) {
                 lob = g.rowo[(int64_t)bn * g.R + rb];
             }
         }
+        if (it < nxc) {
+            // A row whose predecessor in the same plane (y - 1, lane - 1) also
+            // has both face sites occupied is skipped: it joins the same two
+            // components (lane 0 of a chunk that starts inside a y row,
+            // BY > 64, looks at the row before itself)
+            const bool both = fa != NOSITE && fc != NOSITE;
+            bool prev = __shfl_up((int)both, 1, 64) != 0;
+            if (lane == 0) prev = xvalid && yl > 0 && Fs[e - 1] != NOSITE && Gs[e - 1] != NOSITE;
+            if (both && !(yl > 0 && prev)) {
+                if (fa < g.cap && fc < g.cap)
+                    merge_push(g, m, b * g.cap + fa, bxn * g.cap + fc);
+                else
+                    set_err(g, ERR_FACE);
+            }
+        }
+        if (f0 >= cy + cz) continue;
+        // Consecutive face rows of one face are neighbours across the
+        // face's other axis, so a lane at a segment start drops its pair
+        // when the same site of the face row before had the same pair (a
+        // cluster that crosses a face meets the same two components row
+        // after row).
         int sa[MERGE_F], sb[MERGE_F];
         uint64_t sgj[MERGE_F];
 #pragma unroll
