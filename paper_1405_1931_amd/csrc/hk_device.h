@@ -603,7 +603,7 @@ struct CoreOut {
     int nruns;       // runs in the brick
     int btot, itot;  // boundary and interior components of the brick
     int bpre, ipre;  // boundary / interior components whose root run precedes this thread's slice
-    uint64_t rbits;  // start bits of this thread's root runs
+    uint32_t rbits;  // start bits of this thread's root runs, relative to its slice
 };
 
 __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsBrick &s) {
@@ -667,7 +667,7 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
     // wrap): every run of a y or z face row, the run at x = 0 and the last
     // run of a row when it reaches the brick's last x.  The start bits of
     // the slice's root runs are kept for the passes over roots only.
-    uint64_t rbits = 0;
+    uint32_t rbits = 0;
     uint32_t ridm = 0;  // the slice's root runs, bit i for run first + i (a slice holds <= 16 runs)
     {
         const bool frow = (k.hyl && yl == 0) || (k.hyh && yl == k.ey - 1) || (k.hzl && zl == 0) ||
@@ -679,12 +679,13 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
         uint32_t m = (uint32_t)(mine >> (SLICE * q));
         int id = first;
         while (m) {
-            const int sb = __builtin_ctz(m) + SLICE * q;
+            const int b32 = __builtin_ctz(m);
+            const int sb = b32 + SLICE * q;
             m &= m - 1;
             const int v = s.par[id];
             const int r = (v == id || v < 0) ? id : v;
             if (r == id) {
-                rbits |= 1ull << sb;
+                rbits |= 1u << b32;
                 ridm |= 1u << (id - first);
             }
             atomicAdd(&s.par[r], -(run_len(w, sb) << 16));
@@ -772,7 +773,7 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
         const uint64_t w = s.occ[row];
         const uint64_t st = run_starts(w);
         const int q = t % TPR, sh = SLICE * q;
-        uint32_t m = (uint32_t)(co.rbits >> sh);  // root runs only
+        uint32_t m = co.rbits;  // root runs only
         const uint32_t st32 = (uint32_t)(st >> sh);
         // ids of the runs that start below this slice, minus one
         const int base = s.rowoff[row] + __popcll(st & mask_lt(sh)) - 1;
