@@ -1366,36 +1366,65 @@ __device__ __forceinline__ void phase_rank(const Geo &g, int b) {
 // memory per site), then the run offsets of the rows are counted.
 // --------------------------------------------------------------------------
 
+// a copy of a wave-uniform value in a vector register, so that the
+// arithmetic on it runs on the vector pipe
+__device__ __forceinline__ uint32_t vgpr_copy(uint32_t x) {
+    uint32_t v;
+    asm("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
+    return v;
+}
+
 // Expand run labels to sites, one lattice row per wave and one site per
 // lane.  The two forms are kept apart so that the common one (run table in
 // LDS) has no global load in its loop: loads and stores share one
 // outstanding-memory counter, and a load in the loop body makes every row
-// wait for all earlier label stores to drain.
-template <bool RUNS_IN_LDS>
+// wait for all earlier label stores to drain.  The common form is bound by
+// scalar issue, so it has no per-row branch on the lanes (every lane looks
+// up a slot, clamped into the table, and the empty sites discard it) and
+// forms the row address on the vector pipe.
+template <bool RUNS_IN_LDS, bool FULL>
 __device__ __forceinline__ void write_rows(const Geo &g, const Brick &k, const LdsBrick &s, int nc,
                                            const uint16_t *L) {
     const int lane = threadIdx.x & 63;
+    // the lanes past the brick's last x have nothing to store; they leave
+    // (lane 0 stays, so the wave-uniform reads below see a live lane)
+    if (lane >= k.ex) return;
     const int wv = wave_uniform(threadIdx.x >> 6);
     const uint64_t bit = 1ull << lane, le = mask_le(lane);
     const int runmax = g.runcap - 1;
+    int32_t *const col = g.labels + k.x0 + lane;  // the lane's site in lattice row 0
     for (int r = wv; r < g.R; r += NW) {
         const int yl = r & (g.BY - 1), zl = r >> g.lby;
-        if (yl >= k.ey || zl >= k.ez) continue;
+        if (!FULL && (yl >= k.ey || zl >= k.ez)) continue;
         const uint64_t wr = wave_uniform64(s.occ[r]);
         const uint64_t st = run_starts(wr);
         const int off = wave_uniform(s.rowoff[r]) - 1;
-        int32_t *row = g.labels + ((int64_t)(k.z0 + zl) * g.ny + (k.y0 + yl)) * g.nx + k.x0;
         int lab = 0;
-        if (wr & bit) {
+        if constexpr (RUNS_IN_LDS) {
+            const int x = min(max(off + (int)__popcll(st & le), 0), runmax);
+            const int slot = s.par[min(nc + x, MAXRUNS - 1)];
+            const int v = s.par[min(max(slot, 0), MAXRUNS - 1)];
+            lab = (wr & bit) ? v : 0;
+        } else if (wr & bit) {
             const int x = off + (int)__popcll(st & le);
-            const int run = x < runmax ? x : runmax;
-            const int slot = RUNS_IN_LDS ? s.par[nc + run] : L[run];
+            const int slot = L[x < runmax ? x : runmax];
             lab = s.par[min(slot, MAXRUNS - 1)];
         }
+        // rows are below N <= 2^31 - 1: the row index fits 32 bits
+        const uint32_t rowidx = vgpr_copy((uint32_t)((k.z0 + zl) * g.ny + (k.y0 + yl)));
         // the labels are written once and read by nobody in this call:
         // a streaming store, which does not keep the lines in L2
-        if (lane < k.ex) __builtin_nontemporal_store(lab, row + lane);
+        __builtin_nontemporal_store(lab, col + (uint64_t)rowidx * (uint32_t)g.nx);
     }
+}
+
+template <bool RUNS_IN_LDS>
+__device__ __forceinline__ void write_rows(const Geo &g, const Brick &k, const LdsBrick &s, int nc,
+                                           const uint16_t *L) {
+    if (k.ey == g.BY && k.ez == g.BZ)
+        write_rows<RUNS_IN_LDS, true>(g, k, s, nc, L);
+    else
+        write_rows<RUNS_IN_LDS, false>(g, k, s, nc, L);
 }
 
 __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
