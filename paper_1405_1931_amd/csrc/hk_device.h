@@ -1382,6 +1382,13 @@ __device__ __forceinline__ uint32_t vgpr_copy(uint32_t x) {
 // scalar issue, so it has no per-row branch on the lanes (every lane looks
 // up a slot, clamped into the table, and the empty sites discard it) and
 // forms the row address on the vector pipe.
+// v in the lanes whose bit of the wave-uniform mask m is set, else 0
+__device__ __forceinline__ int select_by_mask(uint64_t m, int v) {
+    int r;
+    asm("v_cndmask_b32 %0, 0, %1, %2" : "=v"(r) : "v"(v), "s"(m));
+    return r;
+}
+
 template <bool RUNS_IN_LDS, bool FULL>
 __device__ __forceinline__ void write_rows(const Geo &g, const Brick &k, const LdsBrick &s, int nc,
                                            const uint16_t *L) {
@@ -1390,25 +1397,28 @@ __device__ __forceinline__ void write_rows(const Geo &g, const Brick &k, const L
     // (lane 0 stays, so the wave-uniform reads below see a live lane)
     if (lane >= k.ex) return;
     const int wv = wave_uniform(threadIdx.x >> 6);
-    const uint64_t bit = 1ull << lane, le = mask_le(lane);
     const int runmax = g.runcap - 1;
     int32_t *const col = g.labels + k.x0 + lane;  // the lane's site in lattice row 0
     for (int r = wv; r < g.R; r += NW) {
         const int yl = r & (g.BY - 1), zl = r >> g.lby;
         if (!FULL && (yl >= k.ey || zl >= k.ez)) continue;
         const uint64_t wr = wave_uniform64(s.occ[r]);
-        const uint64_t st = run_starts(wr);
-        const int off = wave_uniform(s.rowoff[r]) - 1;
-        int lab = 0;
+        const int r0 = wave_uniform(s.rowoff[r]);  // id of the row's first run
+        // an occupied site's run: the row's runs that end below it
+        const uint32_t ends = __builtin_amdgcn_mbcnt_hi((uint32_t)((wr & ~(wr >> 1)) >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)(wr & ~(wr >> 1)), 0u));
+        int lab;
         if constexpr (RUNS_IN_LDS) {
-            const int x = min(max(off + (int)__popcll(st & le), 0), runmax);
-            const int slot = s.par[min(nc + x, MAXRUNS - 1)];
-            const int v = s.par[min(max(slot, 0), MAXRUNS - 1)];
-            lab = (wr & bit) ? v : 0;
-        } else if (wr & bit) {
-            const int x = off + (int)__popcll(st & le);
-            const int slot = L[x < runmax ? x : runmax];
-            lab = s.par[min(slot, MAXRUNS - 1)];
+            // every lane looks up a slot (clamped into the table); the empty sites discard it
+            const int slot = s.par[min(nc + r0 + (int)ends, MAXRUNS - 1)];
+            lab = select_by_mask(wr, s.par[min(max(slot, 0), MAXRUNS - 1)]);
+        } else {
+            lab = 0;
+            if ((wr >> lane) & 1ull) {
+                const int x = r0 + (int)ends;
+                const int slot = L[x < runmax ? x : runmax];
+                lab = s.par[min(slot, MAXRUNS - 1)];
+            }
         }
         // rows are below N <= 2^31 - 1: the row index fits 32 bits
         const uint32_t rowidx = vgpr_copy((uint32_t)((k.z0 + zl) * g.ny + (k.y0 + yl)));
