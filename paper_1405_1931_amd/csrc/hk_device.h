@@ -222,6 +222,12 @@ __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_rea
 // the value of lane j (a constant or wave-uniform index), whatever the
 // execution mask; the result is wave-uniform
 __device__ __forceinline__ int lane_value(int v, int j) { return __builtin_amdgcn_readlane(v, j); }
+// the runs of the wave-uniform row word w that end below this lane (the
+// index within the row of the run holding an occupied lane's site)
+__device__ __forceinline__ int runs_ending_below(uint64_t w) {
+    const uint64_t e = w & ~(w >> 1);
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(e >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)e, 0u));
+}
 __device__ __forceinline__ uint64_t lane_value64(uint64_t v, int j) {
     const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, j);
     const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), j);
@@ -1038,11 +1044,11 @@ __device__ __forceinline__ void phase_merge(const Geo &g, int b, MergeLds &m) {
             const uint64_t o = wa & wb;
             sgj[j] = o & ~(o << 1);  // segment starts
             sa[j] = sb[j] = -1;
+            const int ia = oa + runs_ending_below(wa);
+            const int ib = ob + runs_ending_below(wb);
             if ((sgj[j] >> lane) & 1ull) {
                 const int f = f0 + j;
                 const int bn = f < cy ? byn : bzn;
-                const int ia = oa + __popcll(run_starts(wa) & le) - 1;
-                const int ib = ob + __popcll(run_starts(wb) & le) - 1;
                 sa[j] = g.runlab[(int64_t)b * g.runcap + min(ia, g.runcap - 1)];
                 sb[j] = g.runlab[(int64_t)bn * g.runcap + min(ib, g.runcap - 1)];
             }
@@ -1404,18 +1410,16 @@ __device__ __forceinline__ void write_rows(const Geo &g, const Brick &k, const L
         if (!FULL && (yl >= k.ey || zl >= k.ez)) continue;
         const uint64_t wr = wave_uniform64(s.occ[r]);
         const int r0 = wave_uniform(s.rowoff[r]);  // id of the row's first run
-        // an occupied site's run: the row's runs that end below it
-        const uint32_t ends = __builtin_amdgcn_mbcnt_hi((uint32_t)((wr & ~(wr >> 1)) >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)(wr & ~(wr >> 1)), 0u));
+        const int ends = runs_ending_below(wr);  // an occupied site's run within the row
         int lab;
         if constexpr (RUNS_IN_LDS) {
             // every lane looks up a slot (clamped into the table); the empty sites discard it
-            const int slot = s.par[min(nc + r0 + (int)ends, MAXRUNS - 1)];
+            const int slot = s.par[min(nc + r0 + ends, MAXRUNS - 1)];
             lab = select_by_mask(wr, s.par[min(max(slot, 0), MAXRUNS - 1)]);
         } else {
             lab = 0;
             if ((wr >> lane) & 1ull) {
-                const int x = r0 + (int)ends;
+                const int x = r0 + ends;
                 const int slot = L[x < runmax ? x : runmax];
                 lab = s.par[min(slot, MAXRUNS - 1)];
             }
