@@ -82,9 +82,22 @@ void choose_brick(int nx, int ny, int nz, bool batch, int *by, int *bz) {
 // ---------------------------------------------------------------- plans
 
 struct Layout {
-    int64_t occ, root, wpre, face, bcount, npar, nkey, nsize, nlpos, nrootpos, runlab, icomp, icount, nrun,
+    int64_t occ, root, wpre, face, bcount, npar, nkey, nsize, nlpos, nrootkey, runlab, icomp, icount, nrun,
         slab, rowo, rowcnt, blksum, total;
 };
+
+// multiplier and shift of fast_div for the divisor d (1 <= d < 2^31)
+void magic_div(uint32_t d, uint32_t *m, int32_t *l) {
+    if (d <= 1) {
+        *m = 0;
+        *l = 0;
+        return;
+    }
+    int k = 0;
+    while (((uint64_t)1 << k) < d) ++k;  // ceil(log2 d)
+    *m = (uint32_t)((((uint64_t)1 << 32) * (((uint64_t)1 << k) - d)) / d + 1);
+    *l = k;
+}
 
 // geometry (no pointers) of one lattice; false if it cannot be handled
 bool make_geo(int nx, int ny, int nz, uint32_t mask, int by, int bz, Geo *g) {
@@ -117,6 +130,8 @@ bool make_geo(int nx, int ny, int nz, uint32_t mask, int by, int bz, Geo *g) {
     g->fstride = 2 * g->R;
     g->rows = ny * nz;  // <= N <= INT32_MAX
     g->nblk = (int)(((int64_t)g->rows + WG - 1) / WG);
+    magic_div((uint32_t)((int64_t)nx * ny), &g->dm_xy, &g->ds_xy);  // nx ny <= N < 2^31
+    magic_div((uint32_t)nx, &g->dm_x, &g->ds_x);
     return true;
 }
 
@@ -139,7 +154,7 @@ Layout layout_of(const Geo &g, int64_t base) {
     L.nkey = take(nodes * 4);
     L.nsize = take(nodes * 4);
     L.nlpos = take(nodes * 2);
-    L.nrootpos = take(nodes * 8);
+    L.nrootkey = take(nodes * 4);
     L.runlab = take((int64_t)g.nb * g.runcap * 2);
     L.icomp = take((int64_t)g.nb * g.icap * 4);
     L.icount = take((int64_t)g.nb * 4);
@@ -162,7 +177,7 @@ void bind(Geo *g, char *base, const Layout &L) {
     g->nkey = (int32_t *)(base + L.nkey);
     g->nsize = (int32_t *)(base + L.nsize);
     g->nlpos = (uint16_t *)(base + L.nlpos);
-    g->nrootpos = (int64_t *)(base + L.nrootpos);
+    g->nrootkey = (int32_t *)(base + L.nrootkey);
     g->runlab = (uint16_t *)(base + L.runlab);
     g->icomp = (uint32_t *)(base + L.icomp);
     g->icount = (int32_t *)(base + L.icount);

@@ -74,6 +74,10 @@ struct Geo {
     int32_t fstride;  // x-face table entries per brick (2 R)
     int32_t rows;     // ny * nz lattice rows
     int32_t nblk;     // ceil(rows / WG)
+    // division of a site index (below 2^31) by nx * ny and by nx: multiplier
+    // and shift of the round-up method for 32-bit dividends (see fast_div)
+    uint32_t dm_xy, dm_x;
+    int32_t ds_xy, ds_x;
     // caller buffers
     const float *phi;  // the field (float32, or uint8 for PK_U8)
     int32_t tkey;      // order key of the predicate's threshold / value
@@ -90,7 +94,7 @@ struct Geo {
     int32_t *nkey;    // [nb*cap] linear index of the node's lowest site (incremental calls only)
     int32_t *nsize;   // [nb*cap] sites in the node; at a root, the cluster
     uint16_t *nlpos;  // [nb*cap] brick-local position row*64 + x of the key
-    int64_t *nrootpos; // [nb*cap] word index << 6 | bit of the node's root key site
+    int32_t *nrootkey; // [nb*cap] key of the node's root (the linear index of its cluster's lowest site)
     int32_t *nrun;    // [nb] runs of each brick
     uint16_t *runlab; // [nb][runcap] component slot of every run of the brick
     uint32_t *icomp;  // [nb][icap] interior component: size << LPOS_BITS | key position
@@ -1099,8 +1103,8 @@ __device__ __forceinline__ void phase_merge(const Geo &g, int b, MergeLds &m) {
 // them) are first summed per brick in an LDS hash keyed by root node, then
 // added to the root with one global atomic per (brick, root), instead of one
 // per node.  Finds halve paths here; the node's parent entry itself is never
-// finalised (a concurrent halving store could overwrite it): the root
-// position is kept in its own array, written only by the node's thread.
+// finalised (a concurrent halving store could overwrite it): the root's
+// key is kept in its own array, written only by the node's thread.
 // --------------------------------------------------------------------------
 
 constexpr int HT_BITS = 10;  // 1024 slots: 16 KB of LDS with the root words leaves eight workgroups per CU
@@ -1109,32 +1113,27 @@ static_assert(2 * HT <= MAXRUNS, "the hash must fit in the run array of LdsBrick
 
 // Bricks b0 .. b0 + nbr - 1 share the LDS hash, so a root that many bricks
 // reach (the spanning cluster's) receives one global add per group of bricks.
-constexpr int ROOTS_MAX = 4;  // bricks one roots workgroup may take
+constexpr int ROOTS_MAX = 2;  // bricks one roots workgroup may take
 
-// q = v / d and *rem = v - q d, for 0 <= v < 2^31 and d >= 1; inv = 1.0 / d.
-// The product in double precision is within one of the true quotient, and
-// one correction step makes it exact.
-__device__ __forceinline__ int div_exact(int v, int d, double inv, int *rem) {
-    int q = (int)((double)v * inv);
-    int64_t r = (int64_t)v - (int64_t)q * d;
-    if (r < 0) {
-        --q;
-        r += d;
-    } else if (r >= d) {
-        ++q;
-        r -= d;
-    }
-    *rem = (int)r;
-    return q;
+// floor(v / d) for 0 <= v < 2^31 and 1 <= d < 2^31, from the multiplier m
+// and shift l of the round-up method for 32-bit unsigned dividends:
+// l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1, and the quotient is
+// (t + ((v - t) >> 1)) >> (l - 1) with t the high word of m v; d = 1 has
+// l = 0 and is the identity.  The host forms m and l (magic_div in the API).
+__device__ __forceinline__ uint32_t fast_div(uint32_t v, uint32_t m, int l) {
+    if (l == 0) return v;
+    const uint32_t t = __umulhi(m, v);
+    return (t + ((v - t) >> 1)) >> (l - 1);
 }
 
 // word position (word index << 6 | bit) of the site whose linear index is key
-__device__ __forceinline__ int64_t key_word_pos(const Geo &g, int key, double inxy, double inx) {
-    int rxy, x;
-    const int z = div_exact(key, g.nx * g.ny, inxy, &rxy);
-    const int y = div_exact(rxy, g.nx, inx, &x);
-    const int bx = x >> 6, by = y >> g.lby, bz = z >> g.lbz;
-    const int r = (y & (g.BY - 1)) + g.BY * (z & (g.BZ - 1));
+__device__ __forceinline__ int64_t key_word_pos(const Geo &g, int key) {
+    const uint32_t z = fast_div((uint32_t)key, g.dm_xy, g.ds_xy);
+    const uint32_t rxy = (uint32_t)key - z * (uint32_t)(g.nx * g.ny);
+    const uint32_t y = fast_div(rxy, g.dm_x, g.ds_x);
+    const int x = (int)(rxy - y * (uint32_t)g.nx);
+    const int bx = x >> 6, by = (int)y >> g.lby, bz = (int)z >> g.lbz;
+    const int r = ((int)y & (g.BY - 1)) + g.BY * ((int)z & (g.BZ - 1));
     return (((int64_t)((bz * g.nby + by) * g.nbx + bx) * g.R + r) << 6) | (x & 63);
 }
 
@@ -1146,8 +1145,8 @@ __device__ __forceinline__ int64_t key_word_pos(const Geo &g, int key, double in
 //
 // The nodes of all the workgroup's bricks form one index range, two nodes
 // per thread and step; a node's own position and size are requested with
-// its first parent load, and the root's key, which the find returns, gives
-// the position of the root's key site without a further load.
+// its first parent load; the root's key, which the find returns, is kept
+// for the rank phase, which finds the key site's word from it.
 __device__ __forceinline__ void phase_roots(const Geo &g, int b0, int nbr, int32_t *hash, uint64_t *rbits) {
     int32_t *hkey = hash, *hval = hash + HT;
     const int nt = blockDim.x;
@@ -1164,7 +1163,6 @@ __device__ __forceinline__ void phase_roots(const Geo &g, int b0, int nbr, int32
 #pragma unroll
     for (int j = 0; j < ROOTS_MAX; ++j) cpre[j + 1] = cpre[j] + (j < nbh ? g.bcount[b0 + j] : 0);
     const int total = cpre[ROOTS_MAX];
-    const double inxy = 1.0 / ((double)g.nx * g.ny), inx = 1.0 / (double)g.nx;
     __syncthreads();
     for (int i0 = threadIdx.x; i0 < total; i0 += 2 * nt) {
         const bool two = i0 + nt < total;
@@ -1186,15 +1184,13 @@ __device__ __forceinline__ void phase_roots(const Geo &g, int b0, int nbr, int32
         for (int u = 0; u < 2; ++u) {
             if (u == 1 && !two) break;
             const int n = nd[u], r = u ? r1 : r0, lr = u ? lp1 : lp0;
+            g.nrootkey[n] = u ? k1 : k0;
             if (r == n) {
-                const int w = min(lr >> 6, g.R - 1);
-                g.nrootpos[n] = (((int64_t)(b0 + bj[u]) * g.R + w) << 6) | (lr & 63);
                 if ((lr >> 6) < g.R)
                     atomicOr((unsigned long long *)(rbits + bj[u] * g.R + (lr >> 6)), 1ull << (lr & 63));
                 else
                     set_err(g, ERR_RANGE);
             } else {
-                g.nrootpos[n] = key_word_pos(g, u ? k1 : k0, inxy, inx);
                 const int add = u ? sz1 : sz0;
                 int h = (int)(((uint32_t)r * 2654435761u) >> (32 - HT_BITS));
                 bool done = false;
@@ -1282,7 +1278,8 @@ __device__ __forceinline__ void phase_rowpre(const Geo &g, int blk, int32_t *tmp
 // phase: rank -- the final label of every node's cluster: 1 + the rank of the
 // cluster's key site (its lowest site, found by the roots phase) among all
 // key sites in linear order, from the root bit words and the per-word
-// prefixes.  The node that holds its cluster's key site (the root) also
+// prefixes (the key site's word comes from the root's key, which the roots
+// phase kept for every node).  The node that holds its cluster's key site (the root) also
 // writes the cluster's size.  Each thread takes RANK_U nodes at a time and
 // issues all their first loads, then all their dependent word loads, so one
 // brick costs two memory round trips.  Interior components are ranked by the
@@ -1328,7 +1325,7 @@ __device__ __forceinline__ void phase_rank(const Geo &g, int b) {
             sz[u] = 0;
             own[u] = false;
             if (c >= bc) continue;
-            const int64_t pos = g.nrootpos[n0 + c];
+            const int64_t pos = key_word_pos(g, g.nrootkey[n0 + c]);
             const int lp = g.nlpos[n0 + c];
             wi[u] = pos >> 6;
             bit[u] = (int)(pos & 63);
