@@ -125,6 +125,7 @@ struct Request {
     int status = HK_OK;
     State state = State::Pending;
     hipEvent_t ready = nullptr;  // recorded on the producer stream at submission, or null
+    hipStream_t producer = nullptr;  // the stream `ready` was recorded on
     int sim_fail = HK_OK;        // simulated servers: the failure planted on this request
 };
 
@@ -242,8 +243,13 @@ struct hk_server {
         return e;
     }
 
-    // launch the longest prefix of the queue that fits this slot and the arena
-    bool launch(Slot &s) {
+    // launch the longest prefix of the queue that fits this slot and the arena.
+    // Called with `lk` held; the batch is taken under it, then the lock is
+    // released while the batch is planned and enqueued (host work of some
+    // tens of microseconds that submissions need not wait for: only this
+    // thread touches the slot and the taken requests until they finish), and
+    // taken again for the bookkeeping.
+    bool launch(Slot &s, std::unique_lock<std::mutex> &lk) {
         std::vector<uint64_t> take;
         int64_t shares = 0;
         const int64_t now = now_ns();
@@ -301,31 +307,46 @@ struct hk_server {
             char *out = base + r.out_off;
             jobs[j] = hk_job{r.phi, r.nx, r.ny, r.nz, r.mask, (int32_t *)out, kbuf + j, (int64_t *)(out + r.lab_bytes)};
         }
+        // the batch reads each phi only after the work its producer stream had
+        // enqueued when the request was submitted.  Of the requests from one
+        // producer stream the latest event covers the earlier ones (stream
+        // order), so the batch waits once per producer stream.
+        std::vector<hipEvent_t> waits, used;
+        {
+            std::vector<hipStream_t> seen;
+            for (auto it = take.rbegin(); it != take.rend(); ++it) {
+                Request &r = reqs[*it];
+                if (!r.ready) continue;
+                if (std::find(seen.begin(), seen.end(), r.producer) == seen.end()) {
+                    seen.push_back(r.producer);
+                    waits.push_back(r.ready);
+                }
+                used.push_back(r.ready);
+                r.ready = nullptr;
+            }
+        }
+        lk.unlock();
         std::vector<Geo> geos;
         int64_t need = 0;
         int rc = plan_batched(jobs.data(), n, &geos, &need);
         if (rc == HK_OK && need > ws_bytes) rc = HK_ERR_NO_WORKSPACE;
-        // the batch reads each phi only after the work its producer stream had
-        // enqueued when the request was submitted
-        for (uint64_t tk : take) {
-            Request &r = reqs[tk];
-            if (!r.ready) continue;
-            if (rc == HK_OK && hipStreamWaitEvent(s.stream, r.ready, 0) != hipSuccess) rc = HK_ERR_HIP;
-            event_pool.push_back(r.ready);
-            r.ready = nullptr;
-        }
+        for (hipEvent_t e : waits)
+            if (rc == HK_OK && hipStreamWaitEvent(s.stream, e, 0) != hipSuccess) rc = HK_ERR_HIP;
         if (rc == HK_OK && hipMemsetAsync(kbuf + n, 0, (size_t)n * 8, s.stream) != hipSuccess) rc = HK_ERR_HIP;
         if (rc == HK_OK) {
-            std::lock_guard<std::mutex> lk(workspace_mutex());
+            std::lock_guard<std::mutex> wl(workspace_mutex());
             rc = enqueue_batched(jobs.data(), n, geos, block, (int32_t *)(kbuf + n), 8, nullptr, s.stream);
         }
         if (rc == HK_OK &&
             hipMemcpyAsync(s.host, kbuf, (size_t)(2 * n) * 8, hipMemcpyDeviceToHost, s.stream) != hipSuccess)
             rc = HK_ERR_HIP;
         if (rc == HK_OK && hipEventRecord(s.ev, s.stream) != hipSuccess) rc = HK_ERR_HIP;
+        if (rc != HK_OK) (void)hipStreamSynchronize(s.stream);
+        lk.lock();
+        // the events may be recorded again once the stream-ordered waits are enqueued
+        for (hipEvent_t e : used) event_pool.push_back(e);
         if (rc != HK_OK) {
             // nothing observable was launched for these jobs: report and free
-            (void)hipStreamSynchronize(s.stream);
             for (uint64_t tk : take) {
                 Request &r = reqs[tk];
                 arena.release(r.out_off, r.out_bytes);
@@ -361,7 +382,7 @@ struct hk_server {
             if (progress) done_cv.notify_all();
             for (Slot &s : slots) {
                 if (queue.empty()) break;
-                if (!s.busy && launch(s)) progress = true;
+                if (!s.busy && launch(s, lk)) progress = true;
             }
             if (progress) {
                 done_cv.notify_all();
@@ -491,24 +512,37 @@ int submit(hk_server *s, const float *phi, int32_t nx, int32_t ny, int32_t nz, u
     r.arrival = arrival_ns > 0 ? arrival_ns : now_ns();
     // a request that can never fit alone is refused now
     if (r.out_bytes + batch_block_bytes(1, r.ws_bytes) > s->arena.size()) return HK_ERR_TOO_LARGE;
+    bool wake;
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (!s->sim && after) {
-            // phi is complete once the producer stream's present work is
-            r.ready = s->take_event();
-            if (!r.ready || hipEventRecord(r.ready, producer) != hipSuccess) {
-                if (r.ready) s->event_pool.push_back(r.ready);
+            // phi is complete once the producer stream's present work is;
+            // a stream with nothing pending needs no event
+            const hipError_t q = hipStreamQuery(producer);
+            if (q == hipErrorNotReady) {
+                (void)hipGetLastError();
+                r.ready = s->take_event();
+                r.producer = producer;
+                if (!r.ready || hipEventRecord(r.ready, producer) != hipSuccess) {
+                    if (r.ready) s->event_pool.push_back(r.ready);
+                    (void)hipGetLastError();
+                    return HK_ERR_HIP;
+                }
+            } else if (q != hipSuccess) {
                 (void)hipGetLastError();
                 return HK_ERR_HIP;
             }
         }
         const uint64_t t = s->next_ticket++;
         s->reqs.emplace(t, r);
+        // the scheduler waits without a deadline only on an empty queue;
+        // otherwise it looks at the queue again within 20 us by itself
+        wake = s->queue.empty();
         s->queue.push_back(t);
         ++s->submitted;
         *ticket = t;
     }
-    s->work_cv.notify_one();
+    if (wake) s->work_cv.notify_one();
     return HK_OK;
 }
 

@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import ctypes
 
-from . import _lib
+from . import _check_phi, _lib, _stream_handle, mask_of
 
 
 class _DeviceArray:
@@ -63,8 +63,6 @@ class Server:
         The batch that reads phi waits on the device for the work enqueued so
         far on `stream` (default: torch's current stream), so phi may still be
         in the making there."""
-        from . import _check_phi, _stream_handle, mask_of
-
         _check_phi(phi)
         nz, ny, nx = phi.shape
         t = ctypes.c_uint64()
