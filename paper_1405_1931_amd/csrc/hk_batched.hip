@@ -76,7 +76,7 @@ __global__ __launch_bounds__(WG) void kb_rowpre(GroupView v) {
 __global__ __launch_bounds__(WG_RANK) __attribute__((amdgpu_waves_per_eu(8))) void kb_rank(GroupView v) {
     int i;
     const Geo &g = locate(v, 6, blockIdx.x, &i);
-    phase_rank(g, i);
+    phase_rank(g, i, 1);
 }
 
 __global__ __launch_bounds__(WG) void kb_write(GroupView v) {

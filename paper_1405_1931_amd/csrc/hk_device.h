@@ -1306,37 +1306,65 @@ __device__ __forceinline__ int xcd_brick(const Geo &g, int i) {
     return q < g.nby * g.nbz ? q * g.nbx + bx : -1;
 }
 
-__device__ __forceinline__ void phase_rank(const Geo &g, int b) {
-    const int bc = g.bcount[b];
+// the same mapping over groups of RANK_BRICKS consecutive bricks of a
+// brick-row: workgroup i takes the group's first brick (or -1)
+constexpr int RANK_BRICKS = 2;
+__host__ __device__ __forceinline__ int64_t xcd_grid_rank(const Geo &g) {
+    const int64_t q = (int64_t)g.nby * g.nbz;
+    return (int64_t)NXCD * ((g.nbx + RANK_BRICKS - 1) / RANK_BRICKS) * ((q + NXCD - 1) / NXCD);
+}
+__device__ __forceinline__ int xcd_brick_rank(const Geo &g, int i) {
+    const int ng = (g.nbx + RANK_BRICKS - 1) / RANK_BRICKS;
+    const int x = i % NXCD, j = i / NXCD;
+    const int q = x + NXCD * (j / ng), bx = RANK_BRICKS * (j % ng);
+    return q < g.nby * g.nbz ? q * g.nbx + bx : -1;
+}
+
+// Bricks b0 .. b0 + nbr - 1 (consecutive bricks of one brick-row) form one
+// node range: each thread takes up to RANK_U nodes at a time, issues their
+// loads together, then their dependent word loads.
+__device__ __forceinline__ void phase_rank(const Geo &g, int b0, int nbr) {
     const int64_t kmax = (n_sites(g) + 1) / 2;
     const int64_t words = (int64_t)g.nb * g.R;
-    const int64_t wb = (int64_t)b * g.R;
-    const int n0 = b * g.cap;
-    for (int c0 = threadIdx.x; c0 < bc; c0 += RANK_U * WG_RANK) {
+    const int nbh = min(nbr, g.nb - b0);
+    const int bc0 = g.bcount[b0];
+    const int total = bc0 + (nbh > 1 ? g.bcount[b0 + 1] : 0);
+    for (int c0 = threadIdx.x; c0 < total; c0 += RANK_U * WG_RANK) {
+        int n[RANK_U], key[RANK_U], lp[RANK_U];
+        int64_t wb[RANK_U];
+        int32_t sz[RANK_U];
+#pragma unroll
+        for (int u = 0; u < RANK_U; ++u) {
+            const int c = c0 + u * WG_RANK;
+            const int j = c < bc0 ? 0 : 1;
+            n[u] = (b0 + j) * g.cap + (c - (j ? bc0 : 0));
+            wb[u] = (int64_t)(b0 + j) * g.R;
+            key[u] = 0;
+            lp[u] = 0;
+            sz[u] = 0;
+            if (c >= total) continue;
+            key[u] = g.nrootkey[n[u]];
+            lp[u] = g.nlpos[n[u]];
+            sz[u] = g.nsize[n[u]];
+        }
         int64_t wi[RANK_U];
         int bit[RANK_U];
-        int32_t sz[RANK_U];
         bool own[RANK_U];
+        uint64_t rw[RANK_U];
+        int wp[RANK_U];
 #pragma unroll
         for (int u = 0; u < RANK_U; ++u) {
             const int c = c0 + u * WG_RANK;
             wi[u] = -1;
             bit[u] = 0;
-            sz[u] = 0;
             own[u] = false;
-            if (c >= bc) continue;
-            const int64_t pos = key_word_pos(g, g.nrootkey[n0 + c]);
-            const int lp = g.nlpos[n0 + c];
-            wi[u] = pos >> 6;
-            bit[u] = (int)(pos & 63);
-            // the node holds its cluster's key site: it is the root
-            own[u] = wi[u] == wb + min(lp >> 6, g.R - 1) && bit[u] == (lp & 63);
-            sz[u] = g.nsize[n0 + c];
-        }
-        uint64_t rw[RANK_U];
-        int wp[RANK_U];
-#pragma unroll
-        for (int u = 0; u < RANK_U; ++u) {
+            if (c < total) {
+                const int64_t pos = key_word_pos(g, key[u]);
+                wi[u] = pos >> 6;
+                bit[u] = (int)(pos & 63);
+                // the node holds its cluster's key site: it is the root
+                own[u] = wi[u] == wb[u] + min(lp[u] >> 6, g.R - 1) && bit[u] == (lp[u] & 63);
+            }
             const bool ok = wi[u] >= 0 && wi[u] < words;
             rw[u] = ok ? g.root[wi[u]] : 0ull;
             wp[u] = ok ? g.wpre[wi[u]] : 0;
@@ -1344,14 +1372,14 @@ __device__ __forceinline__ void phase_rank(const Geo &g, int b) {
 #pragma unroll
         for (int u = 0; u < RANK_U; ++u) {
             const int c = c0 + u * WG_RANK;
-            if (c >= bc) break;
+            if (c >= total) break;
             if (wi[u] < 0 || wi[u] >= words) {
                 set_err(g, ERR_RANGE);
-                g.slab[n0 + c] = 0;
+                g.slab[n[u]] = 0;
                 continue;
             }
             const int rank = wp[u] + __popcll(rw[u] & mask_lt(bit[u]));
-            g.slab[n0 + c] = rank + 1;
+            g.slab[n[u]] = rank + 1;
             if (g.sizes && own[u]) {
                 if (rank >= 0 && (int64_t)rank < kmax)
                     g.sizes[rank] = (int64_t)sz[u];

@@ -49,8 +49,8 @@ __global__ __launch_bounds__(WG) void k_rowpre(Geo g) {
 // node labels carry little work per brick and no LDS: small workgroups keep
 // eight bricks per CU in flight
 __global__ __launch_bounds__(WG_RANK) __attribute__((amdgpu_waves_per_eu(8))) void k_rank(Geo g) {
-    const int b = xcd_brick(g, blockIdx.x);
-    if (b >= 0) phase_rank(g, b);
+    const int b = xcd_brick_rank(g, blockIdx.x);
+    if (b >= 0) phase_rank(g, b, min(RANK_BRICKS, g.nbx - b % g.nbx));
 }
 
 __global__ __launch_bounds__(WG) void k_write(Geo g) {
@@ -89,7 +89,7 @@ hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev, int pk) {
     mark(5);
     hipLaunchKernelGGL(k_rowpre, dim3(g.nblk), blk, 0, st, g);
     mark(6);
-    hipLaunchKernelGGL(k_rank, dim3((unsigned)xcd_grid(g)), dim3(WG_RANK), 0, st, g);
+    hipLaunchKernelGGL(k_rank, dim3((unsigned)xcd_grid_rank(g)), dim3(WG_RANK), 0, st, g);
     mark(7);
     hipLaunchKernelGGL(k_write, dim3((unsigned)xcd_grid(g)), blk, 0, st, g);
     mark(8);
