@@ -978,7 +978,7 @@ __device__ __forceinline__ void phase_merge(const Geo &g, int b, MergeLds &m) {
     const int eyn = k.by > 0 ? g.BY : g.ny - (g.nby - 1) * g.BY;
     const int ezn = k.bz > 0 ? g.BZ : g.nz - (g.nbz - 1) * g.BZ;
     const int cy = k.hyl ? k.ez : 0, cz = k.hzl ? k.ey : 0;
-    const uint64_t le = mask_le(lane), lt = mask_lt(lane);
+    const uint64_t le = mask_le(lane);
     // Step `it` of a wave takes x-face chunk `it` (64 rows) and y/z face
     // group `it` (MERGE_F face rows); the loads of both that need nothing
     // else are issued together, then the run slots of the y/z segments.
@@ -1057,26 +1057,27 @@ __device__ __forceinline__ void phase_merge(const Geo &g, int b, MergeLds &m) {
                 sb[j] = g.runlab[(int64_t)bn * g.runcap + min(ib, g.runcap - 1)];
             }
         }
-        // the pair of the segment that covers each lane's site, per row
-        int ca = -1, cb = -1;  // at this lane in the previous face row of the same face
+        // the pair (slots a << 16 | b) of the segment that covers each
+        // lane's site, per row: that of the last segment start at or below
+        // the lane.  A segment start's previous segment is the one covering
+        // the lane below it (a start's lower neighbour is not in the
+        // overlap), one DPP wave shift away.
+        int cp = -1;  // the pair covering this lane in the previous face row of the same face
 #pragma unroll
         for (int j = 0; j < MERGE_F; ++j) {
             const int f = f0 + j;
             if (f >= cy + cz) break;
             const uint64_t sg = sgj[j];
             const uint64_t o = lane_value64(lwa, j) & lane_value64(lwb, j);
-            const bool in = (o >> lane) & 1ull;
-            const uint64_t upto = sg & le;   // starts at or below this lane
+            const int pr = (int)(((uint32_t)sa[j] << 16) | ((uint32_t)sb[j] & 0xFFFFu));  // -1 off the starts
+            const uint64_t upto = sg & le;  // starts at or below this lane
             const int cl = upto ? 63 - __clzll(upto) : lane;
-            const int xa = __shfl(sa[j], cl, 64), xb = __shfl(sb[j], cl, 64);
-            const bool seg = (sg >> lane) & 1ull;
-            const uint64_t below = sg & lt;
-            const int pl = below ? 63 - __clzll(below) : lane;
-            const int psa = __shfl(sa[j], pl, 64), psb = __shfl(sb[j], pl, 64);
-            if (seg) {
+            const int xp = __shfl(pr, cl, 64);
+            const int pp = __builtin_amdgcn_update_dpp(-1, xp, 0x138, 0xf, 0xf, false);  // wave_shr:1
+            if ((sg >> lane) & 1ull) {
                 const bool first_of_face = f == 0 || f == cy;
-                const bool same_row = below && psa == sa[j] && psb == sb[j];
-                const bool same_col = j > 0 && !first_of_face && ca == sa[j] && cb == sb[j];
+                const bool same_row = pp == pr;
+                const bool same_col = j > 0 && !first_of_face && cp == pr;
                 if (!same_row && !same_col) {
                     const int bn = f < cy ? byn : bzn;
                     if (sa[j] < g.cap && sb[j] < g.cap)
@@ -1085,8 +1086,7 @@ __device__ __forceinline__ void phase_merge(const Geo &g, int b, MergeLds &m) {
                         set_err(g, ERR_FACE);
                 }
             }
-            ca = in ? xa : -1;
-            cb = in ? xb : -1;
+            cp = ((o >> lane) & 1ull) ? xp : -1;
         }
     }
     __syncthreads();
