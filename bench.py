@@ -878,6 +878,7 @@ def main():
     # largest copy of the run)
     path_gbs = path_bytes / (ms / 1e3) / 1e9
     step_stats, copy_gbs = None, None
+    counted_per_site = None
     if not args.no_profile:
         step_stats = stats(event_times(torch, lambda: hk.label_into(phi, mask, labels, kbuf, sizes), 10))
         copy_gbs = copy_ceiling(torch, phi)
@@ -898,6 +899,10 @@ def main():
                            "amplification": round(t / a, 3) if a else None,
                            "bound": kernel_bound(load_sq(kk, tag), t, kernels[kk] / 1e3, copy_gbs)}
         roofline["per_kernel"] = per or None
+        # bytes per site the whole step moves by the counters, against the
+        # 8 B/site (+ 8 B/cluster) the method must move
+        if per and all(kk in per for kk in kernels):
+            counted_per_site = round(sum(v["traffic"] for v in per.values()) / n, 2)
     result = {
         "metric": "Gsites/s labelled (1024^3 percolation p=0.3116, periodic)",
         "value": round(n / (ms / 1e3) / 1e9, 3),
@@ -916,7 +921,8 @@ def main():
         "path_roofline": {"algorithmic_bytes": path_bytes, "achieved": round(path_gbs, 1),
                           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(path_gbs / HBM_PEAK_GBS, 4),
                           "copy_ceiling": round(copy_gbs, 1) if copy_gbs else None,
-                          "frac_of_copy": round(path_gbs / copy_gbs, 4) if copy_gbs else None},
+                          "frac_of_copy": round(path_gbs / copy_gbs, 4) if copy_gbs else None,
+                          "algorithmic_bytes_per_site": round(path_bytes / n, 2), "counted_bytes_per_site": counted_per_site},
         "roofline": roofline,
         "kernels_ms": kernels,
         "step_stats": step_stats,
