@@ -327,8 +327,9 @@ int hk_debug_counters(hipStream_t stream, int64_t *counts, int32_t n);
  * the request is done (hk_server_poll returns 1) or failed.  hk_server_submit
  * takes phi as complete; when phi may still be in the making on a stream,
  * submit it with hk_server_submit_after and that stream (the legacy null
- * stream included): the server records an event on it at submission and
- * the batch that reads phi waits for that event on the device.  Output
+ * stream included): when that stream has work pending at submission, the
+ * server records an event on it and the batch that reads phi waits for that
+ * event on the device (an idle stream needs no wait).  Output
  * pointers from hk_server_result point into the arena and are valid until
  * hk_server_release of that ticket.  Results are identical to hk_label of
  * the same lattice alone.
