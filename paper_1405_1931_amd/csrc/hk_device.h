@@ -40,8 +40,8 @@ constexpr int MAXRUNS = 32 * RMAX;    // a 64-bit row holds at most 32 runs
 constexpr int LPOS_BITS = RMAX <= 256 ? 14 : 15;  // bits of a brick-local site position row*64+x
 static_assert(RMAX <= 512, "run ids, positions and sizes are packed for at most 512 rows");
 static_assert(64 * RMAX <= (1 << 14), "brick sizes are accumulated as size << 16 in an int32");
-// the node phases (global union-find, node labels) are latency bound and
-// carry little work per brick: small workgroups keep many bricks in flight
+// the roots phase: 512 threads over the nodes of ROOTS_MAX bricks (measured
+// against 128 and 256: more nodes per workgroup keep more finds in flight)
 constexpr int WG_NODES = 512;
 // the merge phase: two waves per brick, sixteen bricks per CU in flight
 constexpr int WG_MERGE = 128;
@@ -1107,7 +1107,7 @@ __device__ __forceinline__ void phase_merge(const Geo &g, int b, MergeLds &m) {
 // key is kept in its own array, written only by the node's thread.
 // --------------------------------------------------------------------------
 
-constexpr int HT_BITS = 10;  // 1024 slots: 16 KB of LDS with the root words leaves eight workgroups per CU
+constexpr int HT_BITS = 10;  // 1024 slots: 8 KB of LDS (with the bricks' root words 12 KB per workgroup)
 constexpr int HT = 1 << HT_BITS;  // hash slots: keys in hash[0, HT), sums in hash[HT, 2 HT)
 static_assert(2 * HT <= MAXRUNS, "the hash must fit in the run array of LdsBrick");
 
