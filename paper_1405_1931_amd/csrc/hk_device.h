@@ -523,7 +523,7 @@ __device__ __forceinline__ void ballot_rows(const Geo &g, int base, int r1, cons
 
 // occupancy of a brick, OCC_U rows in flight per wave
 template <int PK>
-__device__ __forceinline__ void load_occupancy(const Geo &g, const Brick &k, int b, LdsBrick &s) {
+__device__ __forceinline__ void load_occupancy(const Geo &g, const Brick &k, LdsBrick &s) {
     int r0, r1;
     wave_band(g, &r0, &r1);
     for (int base = r0; base < r1; base += OCC_U) {
@@ -918,7 +918,7 @@ __device__ __forceinline__ void local_labels(const Geo &g, const Brick &k, int b
 template <int PK = PK_GT0>
 __device__ __forceinline__ void phase_local(const Geo &g, int b, LdsBrick &s) {
     const Brick k = brick_of(g, b);
-    load_occupancy<PK>(g, k, b, s);
+    load_occupancy<PK>(g, k, s);
     local_labels(g, k, b, s);
 }
 
