@@ -369,8 +369,10 @@ __device__ __forceinline__ int nd_ld(const int32_t *p) {
 }
 
 // Roots of two nodes at once, with their keys: the two pointer chases
-// advance in lockstep, so their loads are in flight together.  Paths are
-// halved: only non-root entries are rewritten, always to an ancestor.
+// advance in lockstep, so their loads are in flight together.  With HALVE
+// the paths are halved: only non-root entries are rewritten, always to an
+// ancestor.
+template <bool HALVE>
 __device__ __forceinline__ void g_find2(const Geo &g, int &x, int &kx, int &y, int &ky) {
     int32_t *par = g.npar;
     const int nn = n_nodes(g);
@@ -399,7 +401,7 @@ __device__ __forceinline__ void g_find2(const Geo &g, int &x, int &kx, int &y, i
                 kx = -1 - gx;
                 dx = true;
             } else {
-                gl_st(par + x, gx);
+                if (HALVE) gl_st(par + x, gx);
                 x = gx;
             }
         }
@@ -412,7 +414,7 @@ __device__ __forceinline__ void g_find2(const Geo &g, int &x, int &kx, int &y, i
                 ky = -1 - gy;
                 dy = true;
             } else {
-                gl_st(par + y, gy);
+                if (HALVE) gl_st(par + y, gy);
                 y = gy;
             }
         }
@@ -428,7 +430,7 @@ __device__ __forceinline__ void g_unite(const Geo &g, int a, int b) {
     }
     for (int i = 0; i < GUARD; ++i) {
         int ka, kb;
-        g_find2(g, a, ka, b, kb);
+        g_find2<true>(g, a, ka, b, kb);
         if (a == b) return;
         if (ka < kb) {
             const int t = a, tk = ka;
@@ -1102,9 +1104,11 @@ __device__ __forceinline__ void phase_merge(const Geo &g, int b, MergeLds &m) {
 // Sizes of clusters that span many bricks (the spanning cluster spans all of
 // them) are first summed per brick in an LDS hash keyed by root node, then
 // added to the root with one global atomic per (brick, root), instead of one
-// per node.  Finds halve paths here; the node's parent entry itself is never
-// finalised (a concurrent halving store could overwrite it): the root's
-// key is kept in its own array, written only by the node's thread.
+// per node.  The finds here only read: every node is found once, and halving
+// stores cost more write traffic than they save the finds that follow (0.33
+// against 0.43 ms at 1024^3; the merge's finds do halve, which shortens the
+// trees these finds climb).  The root's key is kept in its own array, written
+// only by the node's thread.
 // --------------------------------------------------------------------------
 
 constexpr int HT_BITS = 10;  // 1024 slots: 8 KB of LDS (with the bricks' root words 12 KB per workgroup)
@@ -1179,7 +1183,7 @@ __device__ __forceinline__ void phase_roots(const Geo &g, int b0, int nbr, int32
         const int lp0 = g.nlpos[nd[0]], lp1 = g.nlpos[nd[1]];
         const int sz0 = g.nsize[nd[0]], sz1 = g.nsize[nd[1]];
         int r0 = nd[0], r1 = nd[1], k0, k1;
-        g_find2(g, r0, k0, r1, k1);
+        g_find2<false>(g, r0, k0, r1, k1);
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (u == 1 && !two) break;

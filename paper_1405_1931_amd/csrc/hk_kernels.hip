@@ -7,10 +7,9 @@ namespace hk {
 
 // Four bricks per CU need eight waves per SIMD: the LDS allows four (40 KB
 // each), and the compiler is held to the scalar registers of one of eight
-// waves (78 here; the values that no longer fit move to vector register
-// lanes).  Left free it uses 106 and three bricks run per CU; caps of 96
-// and 88 scalar registers (94 and 86 used) still run three (measured: 3.59
-// and 3.04 ms against 2.64 ms at 1024^3).
+// waves (78; the values that no longer fit move to vector register lanes).
+// Left free it uses more and three bricks run per CU, which measured 15-35 %
+// slower at 1024^3.
 template <int PK>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(8))) void k_local(Geo g) {
     __shared__ LdsBrick s;
