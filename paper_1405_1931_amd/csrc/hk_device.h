@@ -680,7 +680,6 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
     // run of a row when it reaches the brick's last x.  The start bits of
     // the slice's root runs are kept for the passes over roots only.
     uint32_t rbits = 0;
-    uint32_t ridm = 0;  // the slice's root runs, bit i for run first + i (a slice holds <= 16 runs)
     {
         const bool frow = (k.hyl && yl == 0) || (k.hyh && yl == k.ey - 1) || (k.hzl && zl == 0) ||
                           (k.hzh && zl == k.ez - 1);
@@ -696,10 +695,7 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
             m &= m - 1;
             const int v = s.par[id];
             const int r = (v == id || v < 0) ? id : v;
-            if (r == id) {
-                rbits |= 1u << b32;
-                ridm |= 1u << (id - first);
-            }
+            if (r == id) rbits |= 1u << b32;
             atomicAdd(&s.par[r], -(run_len(w, sb) << 16));
             if (frow || id == xlo || id == xhi) bflag_set(s, r);
             ++id;
@@ -707,16 +703,17 @@ __device__ __forceinline__ CoreOut brick_core(const Geo &g, const Brick &k, LdsB
     }
     __syncthreads();
 
-    // the slice's components: its root runs, and those flagged boundary (the
-    // flags of the slice's runs are bits first, first + 1, ... of s.bflag);
-    // their prefix over the slices numbers the components in raster order
+    // the slice's components: its root runs, and those flagged boundary.  The
+    // flags of the slice's runs are bits first, first + 1, ... of s.bflag, and
+    // only root runs are ever flagged.  Their prefix over the slices numbers
+    // the components in raster order.
     uint32_t bw = 0;
-    if (ridm) {
+    if (rbits) {
         const int wi = first >> 5, sh = first & 31;
         const uint64_t two = ((uint64_t)(wi + 1 < MAXRUNS / 32 ? s.bflag[wi + 1] : 0u) << 32) | s.bflag[wi];
-        bw = (uint32_t)(two >> sh) & ridm;
+        bw = (uint32_t)(two >> sh) & ((1u << __popcll(mine)) - 1u);  // a slice holds at most 16 runs
     }
-    const int cb = __popc(bw), ci = __popc(ridm) - cb;
+    const int cb = __popc(bw), ci = __popc(rbits) - cb;
     int tot;
     const int pre = block_excl_scan((ci << 16) | cb, s.tmp, &tot);
     CoreOut out;
