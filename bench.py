@@ -351,55 +351,93 @@ def bench_classify(hk, torch, reps=20):
     return out
 
 
-def bench_droplets(hk, torch, reps=50, r_max=40.0, n_bins=80):
+def bench_droplets(hk, torch, phi_big=None, mask_big=7, reps=50, r_max=40.0, n_bins=80):
     """Config 2 (droplets in 512^3, periodic): hk_label, then the droplet-size
-    statistics (Sec. 5) of its sizes.  Times the statistics alone and label +
-    statistics as one pass (HIP events on the launch stream).  The statistics
-    read 8 B per cluster: with a few thousand clusters they are bound by
-    launch latency, not by HBM."""
+    statistics (Sec. 5) of its sizes.  Times the statistics alone, label +
+    statistics as two calls, and hk_label_droplets, which gathers them in the
+    pass that finalises the sizes (HIP events on the launch stream).  The
+    statistics read 8 B per cluster: with a few thousand clusters they are
+    bound by launch latency, not by HBM.  With phi_big (the 1024^3 field),
+    the two forms are also timed there, where K is in the tens of millions."""
     from paper_1405_1931_amd import workloads as W
 
     phi_np, mask = W.config(2)
     phi = torch.from_numpy(phi_np).cuda()
     nz, ny, nx = phi.shape
     n = phi.numel()
-    labels = torch.empty_like(phi, dtype=torch.int32)
-    kbuf = torch.zeros(1, dtype=torch.int64, device="cuda")
-    sizes = torch.empty(max(1, hk.max_clusters(nx, ny, nz)), dtype=torch.int64, device="cuda")
-    hist = torch.empty(n_bins, dtype=torch.int64, device="cuda")
-    counts = torch.empty(2, dtype=torch.int64, device="cuda")
-    sums = torch.empty(3, dtype=torch.float64, device="cuda")
 
-    def stats():
-        hk.droplet_stats_into(sizes, kbuf, 1, r_max, n_bins, hist, counts, sums)
+    def buffers(t):
+        z, y, x = t.shape
+        return (torch.empty_like(t, dtype=torch.int32), torch.zeros(1, dtype=torch.int64, device="cuda"),
+                torch.empty(max(1, hk.max_clusters(x, y, z)), dtype=torch.int64, device="cuda"),
+                torch.empty(n_bins, dtype=torch.int64, device="cuda"), torch.empty(2, dtype=torch.int64, device="cuda"),
+                torch.empty(3, dtype=torch.float64, device="cuda"))
 
-    def both():
-        hk.label_into(phi, mask, labels, kbuf, sizes)
-        stats()
+    def forms(t, m, b, f):
+        labels, kbuf, sizes, hist, counts, sums = b
+        fl, fk, fs, fh, fc, fsum = f
 
+        def stats():
+            hk.droplet_stats_into(sizes, kbuf, 1, r_max, n_bins, hist, counts, sums)
+
+        def both():
+            hk.label_into(t, m, labels, kbuf, sizes)
+            stats()
+
+        def fused():
+            hk.label_droplets_into(t, m, fl, fk, fs, 1, r_max, n_bins, fh, fc, fsum)
+
+        return (("stats", stats), ("label_and_stats", both), ("fused", fused))
+
+    def time_forms(fns, r):
+        res = {}
+        for name, fn in fns:
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(r):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            res[f"{name}_ms"] = round(e0.elapsed_time(e1) / r, 4)
+        return res
+
+    def same(b, f):
+        """the fused form's outputs against the two-call form's"""
+        k = int(b[1].item())
+        assert int(f[1].item()) == k and torch.equal(f[0], b[0]) and torch.equal(f[2][:k], b[2][:k])
+        assert torch.equal(f[3], b[3]) and torch.equal(f[4], b[4]), "fused droplet statistics differ"
+        tol = 4.0 * max(1, k) * 2.0 ** -52
+        for g, e in zip(f[5].tolist(), b[5].tolist()):
+            assert abs(g - e) <= tol * max(1.0, abs(e)), (g, e)
+        return k
+
+    b, f = buffers(phi), buffers(phi)
     out = {"workload": f"droplets {nx}x{ny}x{nz} mask {mask}, r_max {r_max}, {n_bins} bins"}
-    for name, fn in (("stats", stats), ("label_and_stats", both)):
-        for _ in range(3):
-            fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        out[f"{name}_ms"] = round(e0.elapsed_time(e1) / reps, 4)
-    k = int(kbuf.item())
+    out.update(time_forms(forms(phi, mask, b, f), reps))
+    k = same(b, f)
     out["clusters"] = k
     out["label_and_stats_gsites_per_s"] = round(n / out["label_and_stats_ms"] / 1e6, 2)
-    c = counts.tolist()
-    sm = sums.tolist()
+    out["fused_gsites_per_s"] = round(n / out["fused_ms"] / 1e6, 2)
+    c = b[4].tolist()
+    sm = b[5].tolist()
     out["count"], out["mean_radius"] = c[0], round(sm[0] / max(1, c[0]), 4)
     from oracle import droplets as D
 
-    s_np = sizes[:k].cpu().numpy()
+    s_np = b[2][:k].cpu().numpy()
     exp = D.stats(s_np, 1, r_max, n_bins)
-    assert hist.cpu().tolist() == exp[0].tolist() and c == [exp[1], exp[2]], "droplet statistics differ from the oracle"
+    assert b[3].cpu().tolist() == exp[0].tolist() and c == [exp[1], exp[2]], "droplet statistics differ from the oracle"
+    del b, f
+    if phi_big is not None:
+        torch.cuda.empty_cache()
+        b, f = buffers(phi_big), buffers(phi_big)
+        big = {"workload": f"percolation {phi_big.shape[2]}x{phi_big.shape[1]}x{phi_big.shape[0]} mask {mask_big}"}
+        big.update(time_forms(forms(phi_big, mask_big, b, f)[1:], 5))
+        big["clusters"] = same(b, f)
+        out["percolation1024"] = big
+        del b, f
     assert hk.device_error() == 0
     return out
 
@@ -947,7 +985,7 @@ def main():
         log(f"classify: {result['classify']}")
     if not args.no_droplets:
         torch.cuda.empty_cache()
-        result["droplets"] = bench_droplets(hk, torch)
+        result["droplets"] = bench_droplets(hk, torch, phi, mask)
         log(f"droplets: {result['droplets']}")
     if not args.no_incremental:
         torch.cuda.empty_cache()

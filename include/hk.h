@@ -199,6 +199,23 @@ int hk_droplet_stats(const int64_t *sizes, const int64_t *n_clusters, int64_t ma
                      double r_max, int32_t n_bins, int64_t *hist, int64_t *counts, double *sums,
                      hipStream_t stream);
 
+/*
+ * hk_label_droplets: Sec. 2 labelling (as hk_label) with the Sec. 5
+ * droplet statistics gathered in the same pass that finalises the cluster
+ * sizes (no second pass over `sizes`, which may here be NULL).
+ *   phi .. sizes  as for hk_label
+ *   min_size, r_max, n_bins, hist, counts, sums
+ *                 as for hk_droplet_stats, over all K clusters: the same
+ *                 bin counts and counts exactly, the sums of R^k up to the
+ *                 order of summation
+ * hist, counts and sums are written (not accumulated).  Uses the stream's
+ * workspace as hk_label, plus 8 * 256 * (n_bins + 5) bytes.  No host
+ * synchronisation; errors as for hk_label and hk_droplet_stats.
+ */
+int hk_label_droplets(const float *phi, int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask,
+                      int32_t *labels, int64_t *n_clusters, int64_t *sizes, int64_t min_size, double r_max,
+                      int32_t n_bins, int64_t *hist, int64_t *counts, double *sums, hipStream_t stream);
+
 /* ceil(nx*ny*nz / 2): the Sec. 3 bound on the number of clusters, i.e. the
  * capacity `sizes` must have.  0 for invalid edges. */
 int64_t hk_max_clusters(int32_t nx, int32_t ny, int32_t nz);

@@ -316,6 +316,44 @@ def droplet_stats(sizes, n_clusters, min_size=1, r_max=32.0, n_bins=64, stream=N
     return hist, c[0], c[1], sm[0], sm[1], sm[2]
 
 
+def label_droplets_into(phi, mask, labels, n_clusters, sizes, min_size, r_max, n_bins, hist, counts, sums,
+                        stream=None):
+    """Enqueue one labelling with the droplet statistics gathered in the
+    pass that finalises the sizes (hk_label_droplets); sizes may be None.
+    No synchronisation."""
+    _check_phi(phi)
+    nz, ny, nx = phi.shape
+    rc = _lib.load().hk_label_droplets(
+        ctypes.c_void_p(phi.data_ptr()), nx, ny, nz, mask_of(mask),
+        ctypes.c_void_p(labels.data_ptr()), ctypes.c_void_p(n_clusters.data_ptr()),
+        ctypes.c_void_p(sizes.data_ptr()) if sizes is not None else None,
+        int(min_size), float(r_max), int(n_bins),
+        ctypes.c_void_p(hist.data_ptr()), ctypes.c_void_p(counts.data_ptr()), ctypes.c_void_p(sums.data_ptr()),
+        _stream_handle(stream))
+    _lib.check(rc, "hk_label_droplets")
+
+
+def label_droplets(phi, periodic=0, min_size=1, r_max=32.0, n_bins=64, stream=None):
+    """Label one lattice and gather its droplet statistics in the same pass:
+    (labels, K, sizes[K], (hist, count, sum of sizes, sum R, sum R^2, sum R^3))."""
+    import torch
+
+    _check_phi(phi)
+    nz, ny, nx = phi.shape
+    dev = phi.device
+    labels = torch.empty_like(phi, dtype=torch.int32)
+    k = torch.zeros(1, dtype=torch.int64, device=dev)
+    sz = torch.empty(max(1, max_clusters(nx, ny, nz)), dtype=torch.int64, device=dev)
+    hist = torch.empty(n_bins, dtype=torch.int64, device=dev)
+    counts = torch.empty(2, dtype=torch.int64, device=dev)
+    sums = torch.empty(3, dtype=torch.float64, device=dev)
+    label_droplets_into(phi, periodic, labels, k, sz, min_size, r_max, n_bins, hist, counts, sums, stream=stream)
+    kk = int(k.item())
+    c = counts.tolist()
+    sm = sums.tolist()
+    return labels, kk, sz[:kk], (hist, c[0], c[1], sm[0], sm[1], sm[2])
+
+
 def autotune(phi, periodic=0, reps: int = 3, stream=None):
     """Time every candidate brick shape on this lattice and install the
     fastest for its size bucket; returns (by, bz, ms)."""

@@ -93,6 +93,8 @@ _SIGS = {
     "hk_phase_name": (ctypes.c_char_p, [ctypes.c_int32]),
     "hk_classify": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, ctypes.c_uint32, _P, _P, _P, _P, _P]),
     "hk_droplet_stats": (ctypes.c_int, [_P, _P, _I64, _I64, ctypes.c_double, _I32, _P, _P, _P, _P]),
+    "hk_label_droplets": (ctypes.c_int, [_P, _I32, _I32, _I32, ctypes.c_uint32, _P, _P, _P, _I64, ctypes.c_double, _I32,
+                                         _P, _P, _P, _P]),
     "hk_autotune": (ctypes.c_int, [_P, _I32, _I32, _I32, ctypes.c_uint32, _P, _P, _P, _I32, _P,
                                    ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(ctypes.c_float)]),
     "hk_autotune_batched": (ctypes.c_int, [ctypes.POINTER(HkJob), _I32, _I32, _P, ctypes.POINTER(_I32),

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -353,9 +354,24 @@ int64_t hk_workspace_bytes(int32_t nx, int32_t ny, int32_t nz) {
 
 namespace {
 
-// hk_label and hk_label_pred: one lattice, the field read by predicate pk
+// the droplet statistics requested with a labelling (hk_label_droplets)
+struct DsArgs {
+    int64_t min_size;
+    double r_max;
+    int32_t n_bins;
+    int64_t *hist, *counts;
+    double *sums;
+};
+
+// workspace bytes of the statistics' partial accumulators
+int64_t ds_bytes(int n_bins) {
+    return align_up((int64_t)DS_PARTS * (n_bins + 2) * 8) + align_up((int64_t)DS_PARTS * 3 * 8);
+}
+
+// hk_label, hk_label_pred and hk_label_droplets: one lattice, the field read
+// by predicate pk, with the droplet statistics when ds is non-null
 int label_one(const void *field, int pk, int32_t tkey, int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask,
-              int32_t *labels, int64_t *n_clusters, int64_t *sizes, hipStream_t stream) {
+              int32_t *labels, int64_t *n_clusters, int64_t *sizes, hipStream_t stream, const DsArgs *ds = nullptr) {
     if (!field || !labels || !n_clusters) return HK_ERR_INVALID_ARG;
     int rc = check_shape(nx, ny, nz, periodic_mask);
     if (rc != HK_OK) return rc;
@@ -364,13 +380,25 @@ int label_one(const void *field, int pk, int32_t tkey, int32_t nx, int32_t ny, i
     rc = plan_lattice(nx, ny, nz, periodic_mask, &g);
     if (rc != HK_OK) return rc;
     const Layout L = layout_of(g, 0);
+    const int64_t lat = ds ? align_up(L.total) : L.total;
     std::lock_guard<std::mutex> lk(g_ws_mu);
     Workspace *ws = nullptr;
-    rc = get_workspace(stream, L.total, &ws);
+    rc = get_workspace(stream, lat + (ds ? ds_bytes(ds->n_bins) : 0), &ws);
     if (rc != HK_OK) return rc;
     g.err = (int32_t *)ws->base;
     g.dbg = dbg_counters(ws->base);
     bind(&g, ws->base + kErrBytes, L);
+    if (ds) {
+        char *p = ws->base + kErrBytes + lat;
+        g.ds_part = (int64_t *)p;
+        g.ds_psum = (double *)(p + align_up((int64_t)DS_PARTS * (ds->n_bins + 2) * 8));
+        g.ds_hist = ds->hist;
+        g.ds_counts = ds->counts;
+        g.ds_sums = ds->sums;
+        g.ds_min = ds->min_size;
+        g.ds_rmax = ds->r_max;
+        g.ds_nbins = ds->n_bins;
+    }
     g.phi = (const float *)field;
     g.tkey = tkey;
     g.labels = labels;
@@ -389,6 +417,15 @@ extern "C" {
 int hk_label(const float *phi, int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask, int32_t *labels,
              int64_t *n_clusters, int64_t *sizes, hipStream_t stream) {
     return label_one(phi, PK_GT0, 0, nx, ny, nz, periodic_mask, labels, n_clusters, sizes, stream);
+}
+
+int hk_label_droplets(const float *phi, int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask, int32_t *labels,
+                      int64_t *n_clusters, int64_t *sizes, int64_t min_size, double r_max, int32_t n_bins,
+                      int64_t *hist, int64_t *counts, double *sums, hipStream_t stream) {
+    if (!hist || !counts || !sums) return HK_ERR_INVALID_ARG;
+    if (n_bins < 1 || n_bins > DS_MAXBINS || !(r_max > 0.0) || !std::isfinite(r_max)) return HK_ERR_INVALID_ARG;
+    const DsArgs ds{min_size, r_max, n_bins, hist, counts, sums};
+    return label_one(phi, PK_GT0, 0, nx, ny, nz, periodic_mask, labels, n_clusters, sizes, stream, &ds);
 }
 
 int hk_label_pred(const void *field, int32_t predicate, float param, int32_t nx, int32_t ny, int32_t nz,

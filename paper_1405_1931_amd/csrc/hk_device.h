@@ -27,6 +27,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdint.h>
 
 namespace hk {
@@ -115,6 +116,16 @@ struct Geo {
     int32_t *nsize0;    // [nb*cap] size of each node's brick-local component
     uint64_t *rootw0;   // [nb][R] root bits of each brick's interior components
     int64_t *nchanged;  // bricks labelled anew by the call, or null
+    // droplet statistics (Sec. 5) gathered by the rank phase, where every
+    // cluster's final size is at hand (hk_label_droplets; ds_part null: off)
+    int64_t *ds_part;   // [ds_nbins + 2][DS_PARTS] partial bin counts, count, summed size
+    double *ds_psum;    // [3][DS_PARTS] partial sums of R, R^2, R^3
+    int64_t *ds_hist;   // [ds_nbins] out
+    int64_t *ds_counts; // [2] out
+    double *ds_sums;    // [3] out
+    int64_t ds_min;     // clusters of fewer sites are left out
+    double ds_rmax;     // histogram range [0, r_max)
+    int32_t ds_nbins;   // 1 .. DS_MAXBINS
 };
 
 __host__ __device__ __forceinline__ int n_nodes(const Geo &g) { return g.nb * g.cap; }
@@ -1276,6 +1287,127 @@ __device__ __forceinline__ void phase_rowpre(const Geo &g, int blk, int32_t *tmp
 }
 
 // --------------------------------------------------------------------------
+// droplet statistics (Sec. 5): a cluster of s sites as the radius of the
+// sphere of the same volume, R = (3 s / (4 pi))^(1/3).  The histogram bin is
+// decided on the size, not on a computed radius: R >= e <=> s >= (4 pi / 3)
+// e^3, with the thresholds of the edges e_i = i * r_max / n_bins computed in
+// double as c * (e * e * e), c = 4 pi / 3, so the bin counts are exact
+// integers whatever kernel gathers them.  The sums of R^k carry rounding in
+// the order the reduction takes.
+// --------------------------------------------------------------------------
+
+constexpr int DS_MAXBINS = 2048;  // histogram bins at most
+constexpr int DS_PARTS = 256;     // partial accumulators the rank workgroups spread their adds over
+
+// T[i] = threshold of edge i, h[i] = 0, for i < n_bins (all threads call; no barrier)
+__device__ __forceinline__ void ds_init(double r_max, int n_bins, double *T, int32_t *h, int tid, int nt) {
+    const double w = r_max / n_bins;
+    const double c = 4.0 * M_PI / 3.0;
+    for (int i = tid; i < n_bins; i += nt) {
+        const double e = i * w;
+        T[i] = c * (e * e * e);
+        h[i] = 0;
+    }
+}
+
+// per-thread sums of the clusters counted
+struct DsAcc {
+    int64_t cnt = 0, ssum = 0;
+    double sr = 0.0, sr2 = 0.0, sr3 = 0.0;
+};
+
+// count one cluster of s sites (s >= min_size) into the LDS histogram h and acc
+__device__ __forceinline__ void ds_add(DsAcc &a, const double *T, int32_t *h, int n_bins, int64_t min_size, int64_t s) {
+    if (s < min_size) return;
+    const double sd = (double)s;
+    // the number of edges e_1 .. e_{n-1} whose threshold is <= s: T[lo] <= s < T[hi]
+    int lo = 0, hi = n_bins;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (T[mid] <= sd) lo = mid; else hi = mid;
+    }
+    atomicAdd(&h[lo], 1);
+    const double v = sd * (3.0 / (4.0 * M_PI));
+    const double r = cbrt(v);
+    ++a.cnt;
+    a.ssum += s;
+    a.sr += r;
+    a.sr2 += r * r;
+    a.sr3 += v;
+}
+
+constexpr int WG_RANK = 512;
+
+// LDS of a rank workgroup that gathers the statistics
+struct DsLds {
+    double T[DS_MAXBINS];          // edge thresholds
+    int32_t h[DS_MAXBINS];         // the workgroup's bin counts
+    double red[5][WG_RANK / 64];   // per-wave sums
+};
+
+// a 64-bit value moved by one DPP step, as two 32-bit halves (a lane with
+// no source, or in a masked-off row, gets 0)
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint64_t dpp_mov64(uint64_t x) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, CTRL, ROW_MASK, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), CTRL, ROW_MASK, 0xf, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t bits64(int64_t x) { return (uint64_t)x; }
+__device__ __forceinline__ uint64_t bits64(double x) { return (uint64_t)__double_as_longlong(x); }
+__device__ __forceinline__ void from_bits64(uint64_t u, int64_t *x) { *x = (int64_t)u; }
+__device__ __forceinline__ void from_bits64(uint64_t u, double *x) { *x = __longlong_as_double((long long)u); }
+
+// the sum of x (int64 or double) over the wave's 64 lanes (all active), by
+// the steps of wave_incl_scan: lane 63 ends with the total
+template <class T>
+__device__ __forceinline__ T wave_total64(T x) {
+    T y;
+    from_bits64(dpp_mov64<0x111, 0xf>(bits64(x)), &y); x += y;  // row_shr:1
+    from_bits64(dpp_mov64<0x112, 0xf>(bits64(x)), &y); x += y;  // row_shr:2
+    from_bits64(dpp_mov64<0x114, 0xf>(bits64(x)), &y); x += y;  // row_shr:4
+    from_bits64(dpp_mov64<0x118, 0xf>(bits64(x)), &y); x += y;  // row_shr:8
+    from_bits64(dpp_mov64<0x142, 0xa>(bits64(x)), &y); x += y;  // row_bcast:15
+    from_bits64(dpp_mov64<0x143, 0xc>(bits64(x)), &y); x += y;  // row_bcast:31
+    from_bits64(lane_value64(bits64(x), 63), &y);
+    return y;
+}
+
+// the workgroup's counts and sums into partial accumulator blockIdx % DS_PARTS
+// (all threads call; a workgroup that counted nothing adds nothing)
+__device__ __forceinline__ void ds_flush(const Geo &g, const DsAcc &a, DsLds *dl) {
+    if (!__syncthreads_or(a.cnt != 0)) return;
+    const double v[5] = {(double)wave_total64(a.cnt), (double)wave_total64(a.ssum), wave_total64(a.sr),
+                         wave_total64(a.sr2), wave_total64(a.sr3)};  // counts below 2^53: exact
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) dl->red[k][w] = v[k];
+    __syncthreads();
+    const int p = blockIdx.x % DS_PARTS;
+    for (int i = threadIdx.x; i < g.ds_nbins; i += blockDim.x)
+        if (dl->h[i]) atomicAdd((unsigned long long *)(g.ds_part + (int64_t)i * DS_PARTS + p), (unsigned long long)dl->h[i]);
+    if (threadIdx.x < 5) {
+        const int k = threadIdx.x;
+        double t = 0.0;
+        for (int i = 0; i < WG_RANK / 64; ++i) t += dl->red[k][i];
+        if (k < 2) {
+            if (t > 0.0)
+                atomicAdd((unsigned long long *)(g.ds_part + (int64_t)(g.ds_nbins + k) * DS_PARTS + p), (unsigned long long)t);
+        } else if (t != 0.0) {
+            atomicAdd(g.ds_psum + (k - 2) * DS_PARTS + p, t);
+        }
+    }
+}
+
+// the droplet statistics' partial accumulators cleared by workgroup blk of nblk
+__device__ __forceinline__ void ds_clear(const Geo &g, int blk, int nblk) {
+    const int64_t n = (int64_t)DS_PARTS * (g.ds_nbins + 2);
+    for (int64_t i = (int64_t)blk * blockDim.x + threadIdx.x; i < n; i += (int64_t)nblk * blockDim.x) g.ds_part[i] = 0;
+    for (int i = blk * blockDim.x + threadIdx.x; i < 3 * DS_PARTS; i += nblk * blockDim.x) g.ds_psum[i] = 0.0;
+}
+
+// --------------------------------------------------------------------------
 // phase: rank -- the final label of every node's cluster: 1 + the rank of the
 // cluster's key site (its lowest site, found by the roots phase) among all
 // key sites in linear order, from the root bit words and the per-word
@@ -1287,7 +1419,6 @@ __device__ __forceinline__ void phase_rowpre(const Geo &g, int blk, int32_t *tmp
 // write phase from the brick's own words.
 // --------------------------------------------------------------------------
 
-constexpr int WG_RANK = 512;
 constexpr int RANK_U = 4;
 
 // Workgroups are dispatched to the eight XCDs in turn (workgroup i runs on XCD
@@ -1323,13 +1454,17 @@ __device__ __forceinline__ int xcd_brick_rank(const Geo &g, int i) {
 
 // Bricks b0 .. b0 + nbr - 1 (consecutive bricks of one brick-row) form one
 // node range: each thread takes up to RANK_U nodes at a time, issues their
-// loads together, then their dependent word loads.
-__device__ __forceinline__ void phase_rank(const Geo &g, int b0, int nbr) {
+// loads together, then their dependent word loads.  With STATS the
+// workgroup then gathers the droplet statistics of the clusters whose key
+// site lies in its bricks: the root nodes' and the interior components'.
+template <bool STATS = false>
+__device__ __forceinline__ void phase_rank(const Geo &g, int b0, int nbr, DsLds *dl = nullptr) {
     const int64_t kmax = (n_sites(g) + 1) / 2;
     const int64_t words = (int64_t)g.nb * g.R;
     const int nbh = min(nbr, g.nb - b0);
     const int bc0 = g.bcount[b0];
     const int total = bc0 + (nbh > 1 ? g.bcount[b0 + 1] : 0);
+    if constexpr (STATS) ds_init(g.ds_rmax, g.ds_nbins, dl->T, dl->h, threadIdx.x, WG_RANK);
     for (int c0 = threadIdx.x; c0 < total; c0 += RANK_U * WG_RANK) {
         int n[RANK_U], key[RANK_U], lp[RANK_U];
         int64_t wb[RANK_U];
@@ -1388,6 +1523,29 @@ __device__ __forceinline__ void phase_rank(const Geo &g, int b0, int nbr) {
                     set_err(g, ERR_RANGE);
             }
         }
+    }
+    if constexpr (STATS) {
+        // a cluster's key site lies in its root node (the root carries the
+        // smallest key), so the node clusters are the roots, and their entries
+        // still hold -1 - key; the interior components are finished clusters
+        // (the thresholds were set before the rank loop; one barrier orders them)
+        __syncthreads();
+        DsAcc acc;
+        for (int j = 0; j < nbh; ++j) {
+            const int b = b0 + j;
+            const int nn = g.bcount[b], ni = g.icount[b];
+            const uint32_t *ic = g.icomp + (int64_t)b * g.icap;
+            for (int c = threadIdx.x; c < max(nn, ni); c += WG_RANK) {
+                // a node's entry and size and an interior record, loaded together
+                const int n = b * g.cap + c;
+                const int par = c < nn ? g.npar[n] : 0;
+                const int sz = c < nn ? g.nsize[n] : 0;
+                const uint32_t rec = c < ni ? ic[c] : 0u;
+                if (par < 0) ds_add(acc, dl->T, dl->h, g.ds_nbins, g.ds_min, (int64_t)sz);
+                if (c < ni) ds_add(acc, dl->T, dl->h, g.ds_nbins, g.ds_min, (int64_t)(rec >> LPOS_BITS));
+            }
+        }
+        ds_flush(g, acc, dl);
     }
 }
 

@@ -1,13 +1,8 @@
-// Droplet-size statistics (Sec. 5): the sizes of the clusters expressed as
-// the radius of the sphere of the same volume, R = (3 s / (4 pi))^(1/3),
-// binned into a histogram, with the count, the summed size and the sums of
-// R, R^2, R^3 of the clusters of at least min_size sites.
-//
-// The bin of a cluster is decided on its size, not on a computed radius:
-// R >= e <=> s >= (4 pi / 3) e^3, with the thresholds of the bin edges
-// e_i = i * r_max / n_bins computed in double as c * (e * e * e),
-// c = 4 pi / 3 -- so the histogram is an exact integer result.  The sums of
-// R^k are added in whatever order the reduction takes.
+// Droplet-size statistics (Sec. 5) of a sizes array: the count, the summed
+// size, the histogram of the radius of the sphere of the same volume and the
+// sums of R, R^2, R^3 of the clusters of at least min_size sites.  The
+// binning and the per-cluster terms are those of the rank phase's fused form
+// (ds_init, ds_add): the same bins, exactly, for the same sizes.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -15,12 +10,12 @@
 #include <algorithm>
 
 #include "../../include/hk.h"
+#include "hk_device.h"
 
 namespace hk {
 namespace {
 
 constexpr int DS_WG = 256;
-constexpr int DS_MAXBINS = 2048;
 
 __global__ __launch_bounds__(DS_WG) void k_ds_zero(int64_t *hist, int n_bins, int64_t *counts, double *sums) {
     for (int i = blockIdx.x * DS_WG + threadIdx.x; i < n_bins; i += gridDim.x * DS_WG) hist[i] = 0;
@@ -45,42 +40,18 @@ __global__ __launch_bounds__(DS_WG) void k_ds_stats(const int64_t *sizes, const 
     __shared__ double T[DS_MAXBINS];
     __shared__ int32_t h[DS_MAXBINS];
     __shared__ double tmp[DS_WG / 64];
-    const double w = r_max / n_bins;
-    const double c = 4.0 * M_PI / 3.0;
-    for (int i = threadIdx.x; i < n_bins; i += DS_WG) {
-        const double e = i * w;
-        T[i] = c * (e * e * e);
-        h[i] = 0;
-    }
+    ds_init(r_max, n_bins, T, h, threadIdx.x, DS_WG);
     __syncthreads();
     const int64_t k = min(*nk, cap);
-    int64_t cnt = 0, ssum = 0;
-    double sr = 0.0, sr2 = 0.0, sr3 = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * DS_WG + threadIdx.x; i < k; i += (int64_t)gridDim.x * DS_WG) {
-        const int64_t s = sizes[i];
-        if (s < min_size) continue;
-        const double sd = (double)s;
-        // bin: the number of edges e_1 .. e_{n-1} whose threshold is <= s
-        int lo = 0, hi = n_bins;  // T[lo] <= s < T[hi] (T[n_bins] = inf)
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (T[mid] <= sd) lo = mid; else hi = mid;
-        }
-        atomicAdd(&h[lo], 1);
-        const double v = sd * (3.0 / (4.0 * M_PI));
-        const double r = cbrt(v);
-        ++cnt;
-        ssum += s;
-        sr += r;
-        sr2 += r * r;
-        sr3 += v;
-    }
+    DsAcc a;
+    for (int64_t i = (int64_t)blockIdx.x * DS_WG + threadIdx.x; i < k; i += (int64_t)gridDim.x * DS_WG)
+        ds_add(a, T, h, n_bins, min_size, sizes[i]);
     // cnt and ssum fit a double exactly up to 2^53, far above any lattice here
-    const double tc = block_sum_f64((double)cnt, tmp);
-    const double ts = block_sum_f64((double)ssum, tmp);
-    const double t1 = block_sum_f64(sr, tmp);
-    const double t2 = block_sum_f64(sr2, tmp);
-    const double t3 = block_sum_f64(sr3, tmp);
+    const double tc = block_sum_f64((double)a.cnt, tmp);
+    const double ts = block_sum_f64((double)a.ssum, tmp);
+    const double t1 = block_sum_f64(a.sr, tmp);
+    const double t2 = block_sum_f64(a.sr2, tmp);
+    const double t3 = block_sum_f64(a.sr3, tmp);
     for (int i = threadIdx.x; i < n_bins; i += DS_WG)
         if (h[i]) atomicAdd((unsigned long long *)(hist + i), (unsigned long long)h[i]);
     if (threadIdx.x == 0 && tc > 0.0) {

@@ -1,5 +1,7 @@
 // Kernels of the single-lattice path: one workgroup per brick (or per block
 // of WG lattice rows) and one launch per phase, all on the caller's stream.
+#include <algorithm>
+
 #include "hk_device.h"
 #include "hk_launch.h"
 
@@ -32,6 +34,7 @@ __global__ __launch_bounds__(WG_NODES) void k_roots(Geo g) {
 __global__ __launch_bounds__(WG) void k_rowsum(Geo g) {
     __shared__ int32_t tmp[32];
     phase_rowsum(g, blockIdx.x, tmp);
+    if (g.ds_part) ds_clear(g, blockIdx.x, gridDim.x);  // hk_label_droplets: before the rank phase
 }
 
 __global__ __launch_bounds__(WG) void k_scanblk(Geo g) {
@@ -50,6 +53,42 @@ __global__ __launch_bounds__(WG) void k_rowpre(Geo g) {
 __global__ __launch_bounds__(WG_RANK) __attribute__((amdgpu_waves_per_eu(8))) void k_rank(Geo g) {
     const int b = xcd_brick_rank(g, blockIdx.x);
     if (b >= 0) phase_rank(g, b, min(RANK_BRICKS, g.nbx - b % g.nbx));
+}
+
+// the same, gathering the droplet statistics (hk_label_droplets)
+__global__ __launch_bounds__(WG_RANK) __attribute__((amdgpu_waves_per_eu(8))) void k_rank_ds(Geo g) {
+    __shared__ DsLds dl;
+    const int b = xcd_brick_rank(g, blockIdx.x);
+    if (b >= 0) phase_rank<true>(g, b, min(RANK_BRICKS, g.nbx - b % g.nbx), &dl);
+}
+
+// the outputs from the partial accumulators, one workgroup per column (a
+// bin, the count, the summed size, then the three sums of R^k), its
+// DS_PARTS threads one part each
+static_assert(DS_PARTS == 256, "one thread per part");
+__global__ __launch_bounds__(DS_PARTS) void k_ds_combine(Geo g) {
+    __shared__ int64_t ri[DS_PARTS / 64];
+    __shared__ double rd[DS_PARTS / 64];
+    const int c = blockIdx.x, t = threadIdx.x, nc = g.ds_nbins + 2;
+    if (c < nc) {
+        int64_t v = g.ds_part[(int64_t)c * DS_PARTS + t];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((t & 63) == 0) ri[t >> 6] = v;
+        __syncthreads();
+        if (t == 0) {
+            const int64_t s = ri[0] + ri[1] + ri[2] + ri[3];
+            if (c < g.ds_nbins)
+                g.ds_hist[c] = s;
+            else
+                g.ds_counts[c - g.ds_nbins] = s;
+        }
+    } else {
+        double v = g.ds_psum[(c - nc) * DS_PARTS + t];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((t & 63) == 0) rd[t >> 6] = v;
+        __syncthreads();
+        if (t == 0) g.ds_sums[c - nc] = (rd[0] + rd[1]) + (rd[2] + rd[3]);
+    }
 }
 
 __global__ __launch_bounds__(WG) void k_write(Geo g) {
@@ -88,7 +127,12 @@ hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev, int pk) {
     mark(5);
     hipLaunchKernelGGL(k_rowpre, dim3(g.nblk), blk, 0, st, g);
     mark(6);
-    hipLaunchKernelGGL(k_rank, dim3((unsigned)xcd_grid_rank(g)), dim3(WG_RANK), 0, st, g);
+    if (g.ds_part) {
+        hipLaunchKernelGGL(k_rank_ds, dim3((unsigned)xcd_grid_rank(g)), dim3(WG_RANK), 0, st, g);
+        hipLaunchKernelGGL(k_ds_combine, dim3((unsigned)(g.ds_nbins + 5)), dim3(DS_PARTS), 0, st, g);
+    } else {
+        hipLaunchKernelGGL(k_rank, dim3((unsigned)xcd_grid_rank(g)), dim3(WG_RANK), 0, st, g);
+    }
     mark(7);
     hipLaunchKernelGGL(k_write, dim3((unsigned)xcd_grid(g)), blk, 0, st, g);
     mark(8);

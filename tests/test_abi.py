@@ -152,6 +152,29 @@ def test_label_pred_argument_errors_without_gpu(lib):
     assert lib.hk_label_pred(dummy, 0, 0.5, 2048, 2048, 1024, 0, other, other, None, None) == _lib.HK_ERR_TOO_LARGE
 
 
+def test_label_droplets_argument_errors_without_gpu(lib):
+    dummy = ctypes.c_void_p(0x1000)
+    o = [ctypes.c_void_p(0x2000 + 0x100 * i) for i in range(6)]
+    inf = float("inf")
+
+    def call(phi=dummy, nx=4, mask=0, labels=o[0], k=o[1], r_max=8.0, n_bins=8, hist=o[3], counts=o[4], sums=o[5]):
+        return lib.hk_label_droplets(phi, nx, 4, 4, mask, labels, k, o[2], 1, r_max, n_bins, hist, counts, sums, None)
+
+    # the statistics' arguments, as for hk_droplet_stats
+    for r_max, n_bins in ((0.0, 8), (-1.0, 8), (inf, 8), (float("nan"), 8), (8.0, 0), (8.0, 2049)):
+        assert call(r_max=r_max, n_bins=n_bins) == _lib.HK_ERR_INVALID_ARG
+    assert call(hist=None) == _lib.HK_ERR_INVALID_ARG
+    assert call(counts=None) == _lib.HK_ERR_INVALID_ARG
+    assert call(sums=None) == _lib.HK_ERR_INVALID_ARG
+    # the labelling's, as for hk_label
+    assert call(phi=None) == _lib.HK_ERR_INVALID_ARG
+    assert call(labels=None) == _lib.HK_ERR_INVALID_ARG
+    assert call(k=None) == _lib.HK_ERR_INVALID_ARG
+    assert call(nx=0) == _lib.HK_ERR_INVALID_ARG
+    assert call(mask=8) == _lib.HK_ERR_INVALID_ARG
+    assert call(labels=dummy) == _lib.HK_ERR_INVALID_ARG
+
+
 def test_incremental_argument_errors_without_gpu(lib):
     out = ctypes.c_void_p()
     assert lib.hk_incr_create(0, 4, 4, 0, ctypes.byref(out)) == _lib.HK_ERR_INVALID_ARG
