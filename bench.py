@@ -665,7 +665,7 @@ def summarize_trace(db):
         write_trace_summary(fname, title, part, TRACE_CMD)
 
 
-PATH_KERNELS = ("k_local", "k_merge", "k_roots", "k_rowpre", "k_scanblk", "k_rank", "k_write")
+PATH_KERNELS = ("k_local", "k_merge", "k_roots", "k_rowsum", "k_scanblk", "k_rowpre", "k_rank", "k_write")
 
 
 def summarize_pmc(fetch_dir, write_dir, kernel, tag, calib_bytes=1 << 30):

@@ -84,7 +84,7 @@ void choose_brick(int nx, int ny, int nz, bool batch, int *by, int *bz) {
 
 struct Layout {
     int64_t occ, root, wpre, face, bcount, npar, nkey, nsize, nlpos, nrootkey, runlab, icomp, icount, nrun,
-        slab, rowo, blksum, total;
+        slab, rowo, rowcnt, blksum, total;
 };
 
 // multiplier and shift of fast_div for the divisor d (1 <= d < 2^31)
@@ -162,6 +162,7 @@ Layout layout_of(const Geo &g, int64_t base) {
     L.nrun = take((int64_t)g.nb * 4);
     L.slab = take(nodes * 4);
     L.rowo = take(words * 2);
+    L.rowcnt = take((int64_t)g.rows * 4);
     L.blksum = take((int64_t)g.nblk * 4);
     L.total = o - base;
     return L;
@@ -184,6 +185,7 @@ void bind(Geo *g, char *base, const Layout &L) {
     g->nrun = (int32_t *)(base + L.nrun);
     g->slab = (int32_t *)(base + L.slab);
     g->rowo = (uint16_t *)(base + L.rowo);
+    g->rowcnt = (int32_t *)(base + L.rowcnt);
     g->blksum = (int32_t *)(base + L.blksum);
 }
 

@@ -51,11 +51,11 @@ __global__ __launch_bounds__(WG_NODES) void kb_roots(GroupView v) {
     phase_roots(g, i, 1, hash, rbits);
 }
 
-__global__ __launch_bounds__(WG) void kb_rowpre(GroupView v) {
+__global__ __launch_bounds__(WG) void kb_rowsum(GroupView v) {
     __shared__ int32_t tmp[32];
     int i;
     const Geo &g = locate(v, 3, blockIdx.x, &i);
-    phase_rowpre(g, i, tmp);
+    phase_rowsum(g, i, tmp);
 }
 
 __global__ __launch_bounds__(WG) void kb_scanblk(GroupView v) {
@@ -65,18 +65,24 @@ __global__ __launch_bounds__(WG) void kb_scanblk(GroupView v) {
     phase_scanblk(g, tmp);
 }
 
+__global__ __launch_bounds__(WG) void kb_rowpre(GroupView v) {
+    __shared__ int32_t tmp[32];
+    int i;
+    const Geo &g = locate(v, 5, blockIdx.x, &i);
+    phase_rowpre(g, i, tmp);
+}
 
 
 __global__ __launch_bounds__(WG_RANK) __attribute__((amdgpu_waves_per_eu(8))) void kb_rank(GroupView v) {
     int i;
-    const Geo &g = locate(v, 5, blockIdx.x, &i);
+    const Geo &g = locate(v, 6, blockIdx.x, &i);
     phase_rank(g, i, 1);
 }
 
 __global__ __launch_bounds__(WG) void kb_write(GroupView v) {
     __shared__ LdsBrick s;
     int i;
-    const Geo &g = locate(v, 6, blockIdx.x, &i);
+    const Geo &g = locate(v, 7, blockIdx.x, &i);
     phase_write(g, i, s);
 }
 
@@ -112,7 +118,8 @@ TableLayout table_layout(int n) {
 
 int items_of(const Geo &g, int p) {
     switch (p) {
-        case 3: return g.nblk;
+        case 3:
+        case 5: return g.nblk;
         case 4: return 1;
         default: return g.nb;
     }
@@ -218,7 +225,7 @@ void release_batched() {
     g_arena = CaptureArena();
 }
 
-// Enqueue the table upload and the seven grouped kernels of a validated
+// Enqueue the table upload and the eight grouped kernels of a validated
 // batch; `ws` holds at least the bytes validate_and_plan reported.  The
 // caller holds the workspace mutex (it guards the staging ring).
 // Job j's device-check word is at err + j * err_stride bytes (stride 0: one
@@ -267,10 +274,11 @@ int enqueue_batched(const hk_job *jobs, int n_jobs, const std::vector<Geo> &geos
     hipLaunchKernelGGL(kb_local, dim3((unsigned)items[0]), blk, 0, stream, v);
     hipLaunchKernelGGL(kb_merge, dim3((unsigned)items[1]), dim3(WG_MERGE), 0, stream, v);
     hipLaunchKernelGGL(kb_roots, dim3((unsigned)items[2]), small, 0, stream, v);
-    hipLaunchKernelGGL(kb_rowpre, dim3((unsigned)items[3]), blk, 0, stream, v);
+    hipLaunchKernelGGL(kb_rowsum, dim3((unsigned)items[3]), blk, 0, stream, v);
     hipLaunchKernelGGL(kb_scanblk, dim3((unsigned)items[4]), blk, 0, stream, v);
-    hipLaunchKernelGGL(kb_rank, dim3((unsigned)items[5]), dim3(WG_RANK), 0, stream, v);
-    hipLaunchKernelGGL(kb_write, dim3((unsigned)items[6]), blk, 0, stream, v);
+    hipLaunchKernelGGL(kb_rowpre, dim3((unsigned)items[5]), blk, 0, stream, v);
+    hipLaunchKernelGGL(kb_rank, dim3((unsigned)items[6]), dim3(WG_RANK), 0, stream, v);
+    hipLaunchKernelGGL(kb_write, dim3((unsigned)items[7]), blk, 0, stream, v);
     return hipGetLastError() == hipSuccess ? HK_OK : HK_ERR_HIP;
 }
 

@@ -20,7 +20,7 @@
 //           toward the node with the lowest site
 //   roots   flatten node trees, accumulate cluster      [Sec. 3 list traversal
 //           sizes at each root, mark root sites           to the lowest label]
-//   rowpre / scanblk: prefix count of roots            [Sec. 2 compaction to
+//   rowsum / scanblk / rowpre: prefix count of roots    [Sec. 2 compaction to
 //           over occupancy words in linear order          1..n]
 //   write   component slot -> 1 + rank of its root,     [Sec. 2 final pass,
 //           sizes from the root, labels of all sites      Sec. 5 sizes]
@@ -88,7 +88,7 @@ struct Geo {
     // workspace
     uint64_t *occ;    // [nb][R] occupancy words, brick-major
     uint64_t *root;   // [nb][R] bit set at the lowest site of every cluster
-    int32_t *wpre;    // [nb][R] #cluster roots before this word within its block of WG rows, linear order
+    int32_t *wpre;    // [nb][R] #cluster roots before this word, linear order
     uint16_t *face;   // [nb][fstride] node slot at each x-face site of each row
     int32_t *bcount;  // [nb] nodes used by each brick
     int32_t *npar;    // [nb*cap] node parent; at a root, -1 - the root's key (see g_find)
@@ -104,7 +104,8 @@ struct Geo {
     int32_t icap;     // interior component slots per brick
     int32_t *slab;    // [nb*cap] final label of each node's cluster
     uint16_t *rowo;   // [nb][R] id of the first run of each brick row
-    int32_t *blksum;  // [nblk] roots per block of WG rows, then their prefix
+    int32_t *rowcnt;  // [rows] roots per lattice row
+    int32_t *blksum;  // [nblk] roots per block of rows, then their prefix
     int32_t *err;     // sticky check flag
     uint32_t *dbg;    // [DBG_N] fallback counters (see DBG_*), or null
     // incremental relabelling of a field that changes little between calls:
@@ -1137,13 +1138,11 @@ __device__ __forceinline__ uint32_t fast_div(uint32_t v, uint32_t m, int l) {
     return (t + ((v - t) >> 1)) >> (l - 1);
 }
 
-// word position (word index << 6 | bit) of the site whose linear index is
-// key; *row = its lattice row z * ny + y
-__device__ __forceinline__ int64_t key_word_pos(const Geo &g, int key, int *row) {
+// word position (word index << 6 | bit) of the site whose linear index is key
+__device__ __forceinline__ int64_t key_word_pos(const Geo &g, int key) {
     const uint32_t z = fast_div((uint32_t)key, g.dm_xy, g.ds_xy);
     const uint32_t rxy = (uint32_t)key - z * (uint32_t)(g.nx * g.ny);
     const uint32_t y = fast_div(rxy, g.dm_x, g.ds_x);
-    *row = (int)(z * (uint32_t)g.ny + y);
     const int x = (int)(rxy - y * (uint32_t)g.nx);
     const int bx = x >> 6, by = (int)y >> g.lby, bz = (int)z >> g.lbz;
     const int r = ((int)y & (g.BY - 1)) + g.BY * ((int)z & (g.BZ - 1));
@@ -1236,14 +1235,8 @@ __device__ __forceinline__ void phase_roots(const Geo &g, int b0, int nbr, int32
 }
 
 // --------------------------------------------------------------------------
-// phases: prefix count of root bits over words in linear order, in two
-// levels: wpre counts the roots before each word within its block of WG
-// lattice rows (one pass over the words), blksum the roots before each block
-// (a scan of the block totals).  A word's full prefix is the sum of the two.
+// phases: prefix count of root bits over words in linear order
 // --------------------------------------------------------------------------
-
-constexpr int WG_LOG = 9;  // WG = 2^WG_LOG lattice rows per prefix block
-static_assert((1 << WG_LOG) == WG, "prefix blocks are WG rows");
 
 __device__ __forceinline__ int64_t word_base(const Geo &g, int row) {
     const int y = row % g.ny, z = row / g.ny;
@@ -1252,30 +1245,18 @@ __device__ __forceinline__ int64_t word_base(const Geo &g, int row) {
     return ((int64_t)(by + g.nby * bz) * g.nbx) * g.R + (yl + g.BY * zl);
 }
 
-// one thread per lattice row of block blk: the row's root count, its prefix
-// over the block's rows, then the prefix of each of its words (the words are
-// read twice, the second time from cache)
-__device__ __forceinline__ void phase_rowpre(const Geo &g, int blk, int32_t *tmp) {
+__device__ __forceinline__ void phase_rowsum(const Geo &g, int blk, int32_t *tmp) {
     const int row = blk * WG + threadIdx.x;
     int c = 0;
-    int64_t w0 = 0;
     if (row < g.rows) {
-        w0 = word_base(g, row);
+        const int64_t w0 = word_base(g, row);
         for (int bx = 0; bx < g.nbx; ++bx) c += __popcll(g.root[w0 + (int64_t)bx * g.R]);
+        g.rowcnt[row] = c;
     }
-    int tot;
-    int run = block_excl_scan(c, tmp, &tot);
-    if (row < g.rows) {
-        for (int bx = 0; bx < g.nbx; ++bx) {
-            const int64_t i = w0 + (int64_t)bx * g.R;
-            g.wpre[i] = run;
-            run += __popcll(g.root[i]);
-        }
-    }
-    if (threadIdx.x == 0) g.blksum[blk] = tot;
+    const int s = block_sum(c, tmp);
+    if (threadIdx.x == 0) g.blksum[blk] = s;
 }
 
-// the block totals replaced by their exclusive prefix; K = the sum
 __device__ __forceinline__ void phase_scanblk(const Geo &g, int32_t *tmp) {
     int carry = 0;
     for (int base = 0; base < g.nblk; base += WG) {
@@ -1287,6 +1268,22 @@ __device__ __forceinline__ void phase_scanblk(const Geo &g, int32_t *tmp) {
         carry += tot;
     }
     if (threadIdx.x == 0) *g.n_clusters = (int64_t)carry;
+}
+
+__device__ __forceinline__ void phase_rowpre(const Geo &g, int blk, int32_t *tmp) {
+    const int row = blk * WG + threadIdx.x;
+    const int v = row < g.rows ? g.rowcnt[row] : 0;
+    int tot;
+    const int ex = block_excl_scan(v, tmp, &tot);
+    if (row < g.rows) {
+        int run = g.blksum[blk] + ex;
+        const int64_t w0 = word_base(g, row);
+        for (int bx = 0; bx < g.nbx; ++bx) {
+            const int64_t i = w0 + (int64_t)bx * g.R;
+            g.wpre[i] = run;
+            run += __popcll(g.root[i]);
+        }
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -1490,25 +1487,23 @@ __device__ __forceinline__ void phase_rank(const Geo &g, int b0, int nbr, DsLds 
         int bit[RANK_U];
         bool own[RANK_U];
         uint64_t rw[RANK_U];
-        int wp[RANK_U], bp[RANK_U];
+        int wp[RANK_U];
 #pragma unroll
         for (int u = 0; u < RANK_U; ++u) {
             const int c = c0 + u * WG_RANK;
             wi[u] = -1;
             bit[u] = 0;
             own[u] = false;
-            int row = 0;
             if (c < total) {
-                const int64_t pos = key_word_pos(g, key[u], &row);
+                const int64_t pos = key_word_pos(g, key[u]);
                 wi[u] = pos >> 6;
                 bit[u] = (int)(pos & 63);
                 // the node holds its cluster's key site: it is the root
                 own[u] = wi[u] == wb[u] + min(lp[u] >> 6, g.R - 1) && bit[u] == (lp[u] & 63);
             }
-            const bool ok = wi[u] >= 0 && wi[u] < words && (unsigned)row < (unsigned)g.rows;
+            const bool ok = wi[u] >= 0 && wi[u] < words;
             rw[u] = ok ? g.root[wi[u]] : 0ull;
             wp[u] = ok ? g.wpre[wi[u]] : 0;
-            bp[u] = ok ? g.blksum[row >> WG_LOG] : 0;
         }
 #pragma unroll
         for (int u = 0; u < RANK_U; ++u) {
@@ -1519,7 +1514,7 @@ __device__ __forceinline__ void phase_rank(const Geo &g, int b0, int nbr, DsLds 
                 g.slab[n[u]] = 0;
                 continue;
             }
-            const int rank = bp[u] + wp[u] + __popcll(rw[u] & mask_lt(bit[u]));
+            const int rank = wp[u] + __popcll(rw[u] & mask_lt(bit[u]));
             g.slab[n[u]] = rank + 1;
             if (g.sizes && own[u]) {
                 if (rank >= 0 && (int64_t)rank < kmax)
@@ -1641,13 +1636,9 @@ __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
     const uint16_t *L = g.runlab + (int64_t)b * g.runcap;
     if (t < R) {
         const int64_t i = (int64_t)b * R + t;
-        // the word's full prefix: its block's and its own within the block
-        // (rows past a partial brick's edge are not in the lattice)
-        const int yl = t & (g.BY - 1), zl = t >> g.lby;
-        const int64_t lrow = (int64_t)(k.z0 + zl) * g.ny + (k.y0 + yl);
         s.occ[t] = g.occ[i];
         s.rootw[t] = g.root[i];
-        s.wpre[t] = g.wpre[i] + (yl < k.ey && zl < k.ez ? g.blksum[lrow >> WG_LOG] : 0);
+        s.wpre[t] = g.wpre[i];
         s.rowoff[t] = g.rowo[i];
     }
     // Every load is issued before the first wait: slot labels (nodes, from
@@ -1720,7 +1711,7 @@ __device__ __forceinline__ void phase_write(const Geo &g, int b, LdsBrick &s) {
 // store of a phase as a possible write to them.
 // --------------------------------------------------------------------------
 
-constexpr int NPH = 7;  // local, merge, roots, rowpre, scanblk, rank, write
+constexpr int NPH = 8;  // local, merge, roots, rowsum, scanblk, rowpre, rank, write
 
 typedef const __attribute__((address_space(4))) Geo ConstGeo;
 typedef const __attribute__((address_space(4))) int32_t ConstI32;

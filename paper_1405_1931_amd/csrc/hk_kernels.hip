@@ -31,6 +31,11 @@ __global__ __launch_bounds__(WG_NODES) void k_roots(Geo g) {
     phase_roots(g, blockIdx.x * ROOTS_BRICKS, ROOTS_BRICKS, hash, rbits);
 }
 
+__global__ __launch_bounds__(WG) void k_rowsum(Geo g) {
+    __shared__ int32_t tmp[32];
+    phase_rowsum(g, blockIdx.x, tmp);
+    if (g.ds_part) ds_clear(g, blockIdx.x, gridDim.x);  // hk_label_droplets: before the rank phase
+}
 
 __global__ __launch_bounds__(WG) void k_scanblk(Geo g) {
     __shared__ int32_t tmp[32];
@@ -40,7 +45,6 @@ __global__ __launch_bounds__(WG) void k_scanblk(Geo g) {
 __global__ __launch_bounds__(WG) void k_rowpre(Geo g) {
     __shared__ int32_t tmp[32];
     phase_rowpre(g, blockIdx.x, tmp);
-    if (g.ds_part) ds_clear(g, blockIdx.x, gridDim.x);  // hk_label_droplets: before the rank phase
 }
 
 
@@ -97,8 +101,8 @@ __global__ void k_zero_i64(int64_t *p) {
     if (threadIdx.x == 0) *p = 0;
 }
 
-const char *const kPhaseNames[kPhases] = {"k_local", "k_merge", "k_roots", "k_rowpre",
-                                          "k_scanblk", "k_rank", "k_write"};
+const char *const kPhaseNames[kPhases] = {"k_local", "k_merge", "k_roots", "k_rowsum",
+                                          "k_scanblk", "k_rowpre", "k_rank", "k_write"};
 
 hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev, int pk) {
     const dim3 blk(WG), small(WG_NODES);
@@ -117,19 +121,21 @@ hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev, int pk) {
     mark(2);
     hipLaunchKernelGGL(k_roots, dim3((unsigned)(((int64_t)g.nb + ROOTS_BRICKS - 1) / ROOTS_BRICKS)), small, 0, st, g);
     mark(3);
-    hipLaunchKernelGGL(k_rowpre, dim3(g.nblk), blk, 0, st, g);
+    hipLaunchKernelGGL(k_rowsum, dim3(g.nblk), blk, 0, st, g);
     mark(4);
     hipLaunchKernelGGL(k_scanblk, dim3(1), blk, 0, st, g);
     mark(5);
+    hipLaunchKernelGGL(k_rowpre, dim3(g.nblk), blk, 0, st, g);
+    mark(6);
     if (g.ds_part) {
         hipLaunchKernelGGL(k_rank_ds, dim3((unsigned)xcd_grid_rank(g)), dim3(WG_RANK), 0, st, g);
         hipLaunchKernelGGL(k_ds_combine, dim3((unsigned)(g.ds_nbins + 5)), dim3(DS_PARTS), 0, st, g);
     } else {
         hipLaunchKernelGGL(k_rank, dim3((unsigned)xcd_grid_rank(g)), dim3(WG_RANK), 0, st, g);
     }
-    mark(6);
-    hipLaunchKernelGGL(k_write, dim3((unsigned)xcd_grid(g)), blk, 0, st, g);
     mark(7);
+    hipLaunchKernelGGL(k_write, dim3((unsigned)xcd_grid(g)), blk, 0, st, g);
+    mark(8);
     return hipGetLastError();
 }
 

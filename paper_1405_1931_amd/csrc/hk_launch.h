@@ -7,10 +7,10 @@
 
 namespace hk {
 
-constexpr int kPhases = 7;
+constexpr int kPhases = 8;
 extern const char *const kPhaseNames[kPhases];
 
-// enqueue the seven single-lattice phases on `st`; when `ev` is non-null,
+// enqueue the eight single-lattice phases on `st`; when `ev` is non-null,
 // ev[0..kPhases] are recorded on `st` before each kernel and after the last;
 // `pk` selects the occupancy predicate (PK_*) of the brick phase
 hipError_t launch_single(const Geo &g, hipStream_t st, hipEvent_t *ev, int pk = PK_GT0);
