@@ -1299,14 +1299,44 @@ __device__ __forceinline__ void phase_rowpre(const Geo &g, int blk, int32_t *tmp
 constexpr int DS_MAXBINS = 2048;  // histogram bins at most
 constexpr int DS_PARTS = 256;     // partial accumulators the rank workgroups spread their adds over
 
-// T[i] = threshold of edge i, h[i] = 0, for i < n_bins (all threads call; no barrier)
-__device__ __forceinline__ void ds_init(double r_max, int n_bins, double *T, int32_t *h, int tid, int nt) {
+constexpr int DS_TAB = 256;       // sizes below this take R, R^2 and their bin from a table
+
+// R, R^2 and the bin of the sizes 0 .. DS_TAB - 1, computed as ds_add would
+// (most clusters are small, and a cube root in double is the costly step)
+struct DsTab {
+    double r[DS_TAB], r2[DS_TAB];
+    int32_t bin[DS_TAB];
+};
+
+// the bin of a size: the number of edges e_1 .. e_{n-1} whose threshold
+// c * (e * e * e), e = i * w, is <= sd (the thresholds as ds_init stores them)
+__device__ __forceinline__ int ds_bin_of(double sd, double w, int n_bins) {
+    const double c = 4.0 * M_PI / 3.0;
+    int lo = 0, hi = n_bins;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        const double e = mid * w;
+        if (c * (e * e * e) <= sd) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// T[i] = threshold of edge i, h[i] = 0, for i < n_bins, and the small-size
+// table (all threads call; no barrier)
+__device__ __forceinline__ void ds_init(double r_max, int n_bins, double *T, int32_t *h, DsTab *tab, int tid, int nt) {
     const double w = r_max / n_bins;
     const double c = 4.0 * M_PI / 3.0;
     for (int i = tid; i < n_bins; i += nt) {
         const double e = i * w;
         T[i] = c * (e * e * e);
         h[i] = 0;
+    }
+    for (int i = tid; i < DS_TAB; i += nt) {
+        const double sd = (double)i;
+        const double r = cbrt(sd * (3.0 / (4.0 * M_PI)));
+        tab->r[i] = r;
+        tab->r2[i] = r * r;
+        tab->bin[i] = ds_bin_of(sd, w, n_bins);
     }
 }
 
@@ -1317,22 +1347,33 @@ struct DsAcc {
 };
 
 // count one cluster of s sites (s >= min_size) into the LDS histogram h and acc
-__device__ __forceinline__ void ds_add(DsAcc &a, const double *T, int32_t *h, int n_bins, int64_t min_size, int64_t s) {
+__device__ __forceinline__ void ds_add(DsAcc &a, const double *T, int32_t *h, const DsTab *tab, int n_bins,
+                                       int64_t min_size, int64_t s) {
     if (s < min_size) return;
     const double sd = (double)s;
-    // the number of edges e_1 .. e_{n-1} whose threshold is <= s: T[lo] <= s < T[hi]
-    int lo = 0, hi = n_bins;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (T[mid] <= sd) lo = mid; else hi = mid;
+    const double v = sd * (3.0 / (4.0 * M_PI));
+    int lo;
+    double r, r2;
+    if (s >= 0 && s < DS_TAB) {
+        lo = tab->bin[s];
+        r = tab->r[s];
+        r2 = tab->r2[s];
+    } else {
+        // T[lo] <= s < T[hi]
+        lo = 0;
+        int hi = n_bins;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (T[mid] <= sd) lo = mid; else hi = mid;
+        }
+        r = cbrt(v);
+        r2 = r * r;
     }
     atomicAdd(&h[lo], 1);
-    const double v = sd * (3.0 / (4.0 * M_PI));
-    const double r = cbrt(v);
     ++a.cnt;
     a.ssum += s;
     a.sr += r;
-    a.sr2 += r * r;
+    a.sr2 += r2;
     a.sr3 += v;
 }
 
@@ -1342,6 +1383,7 @@ constexpr int WG_RANK = 512;
 struct DsLds {
     double T[DS_MAXBINS];          // edge thresholds
     int32_t h[DS_MAXBINS];         // the workgroup's bin counts
+    DsTab tab;                     // small sizes
     double red[5][WG_RANK / 64];   // per-wave sums
 };
 
@@ -1464,7 +1506,7 @@ __device__ __forceinline__ void phase_rank(const Geo &g, int b0, int nbr, DsLds 
     const int nbh = min(nbr, g.nb - b0);
     const int bc0 = g.bcount[b0];
     const int total = bc0 + (nbh > 1 ? g.bcount[b0 + 1] : 0);
-    if constexpr (STATS) ds_init(g.ds_rmax, g.ds_nbins, dl->T, dl->h, threadIdx.x, WG_RANK);
+    if constexpr (STATS) ds_init(g.ds_rmax, g.ds_nbins, dl->T, dl->h, &dl->tab, threadIdx.x, WG_RANK);
     for (int c0 = threadIdx.x; c0 < total; c0 += RANK_U * WG_RANK) {
         int n[RANK_U], key[RANK_U], lp[RANK_U];
         int64_t wb[RANK_U];
@@ -1541,8 +1583,8 @@ __device__ __forceinline__ void phase_rank(const Geo &g, int b0, int nbr, DsLds 
                 const int par = c < nn ? g.npar[n] : 0;
                 const int sz = c < nn ? g.nsize[n] : 0;
                 const uint32_t rec = c < ni ? ic[c] : 0u;
-                if (par < 0) ds_add(acc, dl->T, dl->h, g.ds_nbins, g.ds_min, (int64_t)sz);
-                if (c < ni) ds_add(acc, dl->T, dl->h, g.ds_nbins, g.ds_min, (int64_t)(rec >> LPOS_BITS));
+                if (par < 0) ds_add(acc, dl->T, dl->h, &dl->tab, g.ds_nbins, g.ds_min, (int64_t)sz);
+                if (c < ni) ds_add(acc, dl->T, dl->h, &dl->tab, g.ds_nbins, g.ds_min, (int64_t)(rec >> LPOS_BITS));
             }
         }
         ds_flush(g, acc, dl);

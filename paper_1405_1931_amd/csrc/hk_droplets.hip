@@ -40,12 +40,13 @@ __global__ __launch_bounds__(DS_WG) void k_ds_stats(const int64_t *sizes, const 
     __shared__ double T[DS_MAXBINS];
     __shared__ int32_t h[DS_MAXBINS];
     __shared__ double tmp[DS_WG / 64];
-    ds_init(r_max, n_bins, T, h, threadIdx.x, DS_WG);
+    __shared__ DsTab tab;
+    ds_init(r_max, n_bins, T, h, &tab, threadIdx.x, DS_WG);
     __syncthreads();
     const int64_t k = min(*nk, cap);
     DsAcc a;
     for (int64_t i = (int64_t)blockIdx.x * DS_WG + threadIdx.x; i < k; i += (int64_t)gridDim.x * DS_WG)
-        ds_add(a, T, h, n_bins, min_size, sizes[i]);
+        ds_add(a, T, h, &tab, n_bins, min_size, sizes[i]);
     // cnt and ssum fit a double exactly up to 2^53, far above any lattice here
     const double tc = block_sum_f64((double)a.cnt, tmp);
     const double ts = block_sum_f64((double)a.ssum, tmp);
