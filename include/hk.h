@@ -69,6 +69,9 @@ typedef enum {
  *   sizes        int64, device, out: sizes[k-1] = #sites with label k for
  *                k = 1..K; must hold hk_max_clusters(nx, ny, nz) entries;
  *                entries >= K are left untouched.  May be NULL.
+ * The call enqueues kernels only (no copies, no memsets), so it may be
+ * captured into a hipGraph once the stream's workspace is large enough
+ * (an earlier call of the same shape on the stream, or hk_reserve).
  */
 int hk_label(const float *phi, int32_t nx, int32_t ny, int32_t nz, uint32_t periodic_mask,
              int32_t *labels, int64_t *n_clusters, int64_t *sizes, hipStream_t stream);
@@ -143,7 +146,7 @@ typedef struct {
  * hk_label_batched: label n_jobs independent lattices of any shapes with one
  * launch per phase on `stream`, each covering the bricks of every job (the
  * job table itself is a HOST array; it is copied to the device by the call,
- * from pinned memory, so a captured call is one copy node and seven kernel
+ * from pinned memory, so a captured call is one copy node and eight kernel
  * nodes).  Each job's output is
  * identical to what hk_label gives for it alone.  Every job is validated
  * before anything is enqueued.  n_jobs == 0 is a no-op.

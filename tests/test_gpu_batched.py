@@ -156,3 +156,46 @@ def test_autotune_installs_a_shape_and_keeps_results_exact(hk, tmp_path):
         nz, ny, nx = phi_np.shape
         hk.set_brick_for_shape(nx, ny, nz, 0, 0)
     assert hk.device_error() == 0
+
+
+def test_single_lattice_graph_capture_replay(hk):
+    """hk_label enqueues kernels only: captured in a hipGraph once the stream's
+    workspace exists, every replay (into cleared outputs, with the stream's
+    own eager work between replays) equals the eager call, which equals the
+    oracle; two lattices of different shapes and masks, each its own graph."""
+    cases = ((W.percolation((45, 61, 77), 0.3116, seed=51), 5), (W.percolation((64, 64, 64), 0.45, seed=52), 7))
+    s = torch.cuda.Stream()
+    for phi_np, m in cases:
+        print(f"[graph] hk_label capture, shape {phi_np.shape} mask {m}", flush=True)
+        phi = torch.from_numpy(phi_np).cuda()
+        nz, ny, nx = phi.shape
+        labels = torch.empty_like(phi, dtype=torch.int32)
+        k = torch.zeros(1, dtype=torch.int64, device="cuda")
+        sizes = torch.empty(hk.max_clusters(nx, ny, nz), dtype=torch.int64, device="cuda")
+        with torch.cuda.stream(s):
+            hk.label_into(phi, m, labels, k, sizes, stream=s)
+        s.synchronize()
+        ek = int(k.item())
+        el, es = labels.clone(), sizes[:ek].clone()
+        ol, ok, osz = oracle.label(phi_np, m)
+        assert ek == ok and np.array_equal(el.cpu().numpy(), ol) and np.array_equal(es.cpu().numpy(), osz)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            hk.label_into(phi, m, labels, k, sizes, stream=s)
+        for rep in range(4):
+            labels.fill_(-1)
+            k.fill_(-1)
+            sizes.fill_(-1)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert int(k.item()) == ek, rep
+            assert torch.equal(labels, el), rep
+            assert torch.equal(sizes[:ek], es), rep
+            # eager work of the same stream between replays
+            with torch.cuda.stream(s):
+                hk.label_into(phi, m, labels, k, sizes, stream=s)
+            s.synchronize()
+            assert int(k.item()) == ek and torch.equal(labels, el), rep
+        del g
+    assert hk.device_error(stream=s) == 0
